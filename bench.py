@@ -1,0 +1,214 @@
+"""Krylov vectors per second at 200^3 on one MI355X.
+
+One step = one Krylov vector (eqs. 8-10): the linearized momentum stencil, the
+SIMPLE projection (divergence, tensor-product pressure-correction solve,
+velocity/pressure correction, divergence certificate) to a relative divergence
+residual rho <= 1e-8, on a 200^3 tanh-stretched grid (centre/wall spacing 10),
+Re = 1900, lid along x.  Inputs are seeded (SplitMix64) and resident in HBM
+before the timed region.
+
+    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--size 200] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+PEAK_FP64_VECTOR_TFLOPS = 78.6
+RE = 1900.0
+TANH_RATIO = 10.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--size", type=int, default=200)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-sample", type=int, default=2, help="oracle Krylov vectors timed on the host")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def make_inputs(ctx, torch, n_vec, seed0=1):
+    """v_s = P(r_s)/|P(r_s)| with r_s uniform [-1, 1) on interior faces (seeded)."""
+    import synth
+    vs = []
+    for s in range(seed0, seed0 + n_vec):
+        r = torch.from_numpy(synth.random_velocity(ctx.nx, ctx.ny, ctx.nz, s)).cuda()
+        v, _, st = ctx.project(r, tol=1e-12, max_iter=4)
+        v /= torch.linalg.vector_norm(v)
+        vs.append(v)
+    return vs
+
+
+def synthetic_base_flow(ctx, torch):
+    """A seeded divergence-free field with max |U| = 1 (the Krylov-vector cost
+    does not depend on the values of U)."""
+    import synth
+    r = torch.from_numpy(synth.random_velocity(ctx.nx, ctx.ny, ctx.nz, 1000)).cuda()
+    U, _, _ = ctx.project(r, tol=1e-12, max_iter=4)
+    U /= U.abs().max()
+    return U
+
+
+def time_form(ctx, torch, inputs, warmup, steps, precision):
+    vo = ctx.vel()
+    po = ctx.cells()
+    for q in range(warmup):
+        ctx.krylov_vector(inputs[q % len(inputs)], vo, po, precision=precision, tol=1e-8)
+    torch.cuda.synchronize()
+    iters = []
+    t0 = time.perf_counter()
+    for q in range(steps):
+        _, _, st = ctx.krylov_vector(inputs[warmup + q], vo, po, precision=precision, tol=1e-8)
+        if not st["converged"]:
+            raise RuntimeError(f"step {q} did not converge: {st}")
+        iters.append(st["iterations"])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return dt, iters
+
+
+def kernel_table(prof, n):
+    """Per-kernel average durations and algorithmic rates."""
+    nx = ny = nz = n
+    ncell = nx * ny * nz
+    fu = 8.0 * ((nx + 1) * ny * nz + nx * (ny + 1) * nz + nx * ny * (nz + 1))  # bytes of a velocity
+    fp = 8.0 * ncell
+    alg = {
+        "momentum": ("hbm", 3 * fu),             # read U, v; write w
+        "divergence": ("hbm", fu + fp),          # read v; write r
+        "correct": ("hbm", 2 * fu + 2 * fp),     # read w, phi; write v, p
+        "tp_x": ("alu", 2.0 * nx * nx * ny * nz),
+        "tp_y": ("alu", 2.0 * ny * ny * nx * nz),
+        "tp_z": ("alu", 2.0 * nz * nz * nx * ny),
+        "eigscale": ("hbm", 2 * fp),
+    }
+    table = {}
+    for name, (ms, launches) in prof.items():
+        avg = ms / launches
+        row = {"avg_ms": avg, "launches": launches, "total_ms": ms}
+        if name in alg:
+            kind, amount = alg[name]
+            if kind == "hbm":
+                row["GB/s"] = amount / (avg * 1e-3) / 1e9
+                row["frac_hbm"] = row["GB/s"] / PEAK_HBM_GBS
+            else:
+                row["TFLOP/s"] = amount / (avg * 1e-3) / 1e12
+                row["frac_fp64"] = row["TFLOP/s"] / PEAK_FP64_VECTOR_TFLOPS
+            row["algorithmic"] = amount
+        table[name] = row
+    return table
+
+
+def cpu_baseline(n, sample):
+    """The oracle (numpy/scipy, float64) on the host cores: Krylov vectors/s."""
+    import numpy as np
+    import synth
+    from oracle import simple
+    from oracle.grid import Grid
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    except Exception:
+        threads = os.cpu_count()
+    g = Grid.make(n, kind="tanh", ratio=TANH_RATIO)
+    P = simple.Projector(g)
+    U = synth.random_velocity(n, n, n, 1000)
+    U, _ = P.project(U)
+    U /= np.max(np.abs(U))
+    vs = [synth.random_velocity(n, n, n, s) for s in range(1, sample + 1)]
+    t0 = time.perf_counter()
+    for v in vs:
+        P.krylov_vector(U, v, RE)
+    dt = time.perf_counter() - t0
+    return {"value": sample / dt, "unit": "Krylov vectors/s", "cores": threads, "kind": "oracle",
+            "sample": f"{sample} Krylov vectors at {n}^3 tanh-10, Re={RE:g} (numpy float64; "
+                      f"stencils single-threaded, transforms on {threads} BLAS threads)",
+            "seconds": dt}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {a.gpus} is not supported "
+              "(the multi-GPU layout is a design note, not a build)", file=sys.stderr)
+        sys.exit(1)
+    import torch
+    import paper_1704_08521_amd as lk
+    n = a.size
+    torch.cuda.set_device(0)
+    ctx = lk.Context(n, n, n)
+    ctx.set_stretching("tanh", TANH_RATIO)
+    ctx.set_re(RE)
+    ctx.set_lid(0.0)
+    log(f"[bench] {n}^3 tanh-{TANH_RATIO:g} Re={RE:g}: building inputs")
+    U = synthetic_base_flow(ctx, torch)
+    ctx.set_base_flow(U)
+    inputs = make_inputs(ctx, torch, a.warmup + a.steps)
+    torch.cuda.synchronize()
+
+    forms = {}
+    for name, prec in (("plain", lk.FP64), ("mixed", lk.MIXED)):
+        dt, iters = time_form(ctx, torch, inputs, a.warmup, a.steps, prec)
+        forms[name] = {"value": a.steps / dt, "ms_per_step": 1e3 * dt / a.steps,
+                       "simple_passes_mean": sum(iters) / len(iters)}
+        log(f"[bench] {name}: {forms[name]['value']:.1f} vectors/s, {forms[name]['ms_per_step']:.3f} ms/step, "
+            f"passes {forms[name]['simple_passes_mean']:.2f}")
+
+    # profiled repeat of the plain timed loop: per-kernel HIP events on the context stream
+    ctx.profile(True)
+    time_form(ctx, torch, inputs, 0, a.steps, lk.FP64)
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    table = kernel_table(prof, n)
+    dom = max((k for k in table if "algorithmic" in table[k]), key=lambda k: table[k]["total_ms"])
+    d = table[dom]
+    if "TFLOP/s" in d:
+        roof = {"bound": "alu", "achieved": d["TFLOP/s"], "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                "frac": d["frac_fp64"], "traffic": None, "kernel": dom, "avg_ms": d["avg_ms"]}
+    else:
+        roof = {"bound": "hbm", "achieved": d["GB/s"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": d["frac_hbm"], "traffic": None, "kernel": dom, "avg_ms": d["avg_ms"]}
+
+    out = {
+        "metric": "Krylov vectors/s to 1e-8 rel. residual at 200^3 (plain/mixed/learned); % HBM peak",
+        "value": forms["plain"]["value"],
+        "unit": "Krylov vectors/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": forms["plain"]["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"krylov_vector {n}^3 tanh-10 stretched, Re={RE:g}, alpha=0, rho<=1e-8, "
+                               "seeded projected random inputs, synthetic divergence-free base flow",
+                   "grid": [n, n, n], "stretching": "tanh", "ratio": TANH_RATIO, "re": RE, "tol": 1e-8,
+                   "poisson": "tensor-product factorization"},
+        "forms": forms,
+        "roofline": roof,
+        "kernels": table,
+    }
+    if not a.no_cpu:
+        log(f"[bench] cpu baseline: {a.cpu_sample} oracle Krylov vectors at {n}^3")
+        out["cpu_baseline"] = cpu_baseline(n, a.cpu_sample)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,193 @@
+/*
+ * lidkrylov -- SIMPLE-evaluated Krylov vectors for the linear stability of the
+ * lid-driven flow in a cube (Gelfgat, "Linear instability of the lid-driven flow
+ * in a cubic cavity"), on one AMD Instinct MI355X (gfx950).
+ *
+ * C ABI.  Every field argument is a caller-owned DEVICE pointer (e.g. the
+ * data_ptr() of a contiguous torch tensor on the GPU), 8-byte aligned, holding
+ * IEEE float64 values, unless a comment says "host".  Field layout, x fastest
+ * (C order), for an Nx x Ny x Nz grid of finite volumes:
+ *
+ *   u : [Nz][Ny][Nx+1]   x-faces, i = 0 and i = Nx are walls
+ *   v : [Nz][Ny+1][Nx]   y-faces, j = 0 and j = Ny are walls
+ *   w : [Nz+1][Ny][Nx]   z-faces, k = 0 and k = Nz are walls
+ *   p : [Nz][Ny][Nx]     cell centres
+ *
+ * A "velocity" argument is the packed vector u|v|w of
+ * lc_vel_size() = (Nx+1)NyNz + Nx(Ny+1)Nz + NxNy(Nz+1) doubles; a "cell"
+ * argument holds NxNyNz doubles.  Wall-normal faces of velocity inputs are
+ * ignored (read as zero); every velocity output has exact zeros there.
+ *
+ * Execution: one context per stream; calls enqueue on the context's HIP stream
+ * and return when their outputs are valid (convergence control reads scalar
+ * reductions back to the host).  Contexts are not thread-safe.  Inputs and
+ * outputs of one call must not alias unless a comment allows it.  The library
+ * owns its scratch device memory (allocated in lc_create / lc_set_grid, freed in
+ * lc_destroy).
+ *
+ * Return codes: LC_OK = 0; LC_ENOTCONV = 1 (outputs valid, tolerance not met);
+ * negative values are errors, the message is in lc_last_error().
+ */
+#ifndef LIDKRYLOV_H
+#define LIDKRYLOV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LC_OK 0
+#define LC_ENOTCONV 1
+#define LC_EINVAL (-1)  /* bad size, pointer, value, or non-finite input      */
+#define LC_ESTATE (-2)  /* grid, Re or base flow not set                      */
+#define LC_EHIP (-3)    /* HIP runtime error                                  */
+#define LC_ENOMEM (-4)  /* device allocation failed                           */
+
+/* Stretching kinds for lc_set_stretching. */
+#define LC_UNIFORM 0 /* x_i = i/N                                             */
+#define LC_SINE 1    /* Section 3, eq. 5: x_i -> x_i - 0.0975 sin(2 pi x_i)   */
+#define LC_TANH 2    /* x = (1 + tanh(b(2xi-1))/tanh b)/2, cosh^2 b = param    */
+
+/* Precision forms of the pressure-correction solve. */
+#define LC_FP64 0  /* plain: every step in float64                            */
+#define LC_MIXED 1 /* float32 tensor-product solves inside float64 refinement */
+
+/* Pressure-correction Poisson solvers. */
+#define LC_POISSON_TP 0 /* full tensor-product factorization (default)        */
+
+typedef struct lc_ctx lc_ctx;
+
+typedef struct {
+  int iterations;     /* SIMPLE passes (projection corrections) performed      */
+  double rho;         /* final |D v|_V / |D w|_V (volume-weighted L2)          */
+  double rho0;        /* |D w|_V, the divergence of the uncorrected vector     */
+  double rho_hist[16];/* rho after each pass                                   */
+  double ms_total;    /* wall time of the call, host clock                     */
+} lc_stats;
+
+/* Library version string (static storage). */
+const char* lc_version(void);
+
+/* Message of the last error on this context (or of the last failed lc_create
+ * when ctx is NULL).  Static or context-owned storage. */
+const char* lc_last_error(const lc_ctx* ctx);
+
+/* Create a context for an nx x ny x nz grid (each >= 2, <= 4096) on the HIP
+ * stream `hip_stream` (hipStream_t, NULL = default stream) of the current
+ * device.  The grid starts uniform, Re = 1, lid angle 0, base flow zero. */
+int lc_create(lc_ctx** out, int nx, int ny, int nz, void* hip_stream);
+int lc_destroy(lc_ctx* ctx);
+int lc_set_stream(lc_ctx* ctx, void* hip_stream);
+
+/* Number of doubles in a packed velocity / a cell field. */
+size_t lc_vel_size(const lc_ctx* ctx);
+size_t lc_cell_size(const lc_ctx* ctx);
+
+/* Face coordinates (host arrays of nx+1, ny+1, nz+1 doubles, strictly
+ * increasing from 0 to 1) -- the N+1 grid points per direction of Section 3.
+ * Rebuilds the metrics and the tensor-product Poisson factorization. */
+int lc_set_grid(lc_ctx* ctx, const double* xf, const double* yf, const double* zf);
+
+/* Generate the faces of every axis with one stretching (LC_UNIFORM, LC_SINE,
+ * LC_TANH with param = centre/wall spacing ratio > 1) and call lc_set_grid. */
+int lc_set_stretching(lc_ctx* ctx, int kind, double param);
+
+/* Copy the faces out (host arrays of nx+1, ny+1, nz+1 doubles). */
+int lc_get_grid(const lc_ctx* ctx, double* xf, double* yf, double* zf);
+
+/* Reynolds number Re = UL/nu (Section 2), re > 0. */
+int lc_set_re(lc_ctx* ctx, double re);
+
+/* Lid direction: u = cos(alpha), v = sin(alpha) at z = 1 (Section 2, eq. 4). */
+int lc_set_lid(lc_ctx* ctx, double alpha_rad);
+
+/* Base flow U (velocity, device) about which eq. 6 is linearized; copied. */
+int lc_set_base_flow(lc_ctx* ctx, const double* U);
+/* Copy the base flow out (velocity, device). */
+int lc_get_base_flow(const lc_ctx* ctx, double* U);
+
+/* ---------------------------------------------------------------- stencils */
+
+/* Right side of eq. 10, the linearized momentum (eq. 6) applied to v:
+ * w = Re^-1 Lap v - (U.grad)v - (v.grad)U with homogeneous wall values, in the
+ * conservative staggered form.  v, w: velocity. */
+int lc_jacobian_apply(lc_ctx* ctx, const double* v, double* w);
+
+/* Momentum residual of eq. 2 at steady state without pressure:
+ * R(U) = Re^-1 Lap U - (U.grad)U with the lid of eq. 4.  U, R: velocity. */
+int lc_residual(lc_ctx* ctx, const double* U, double* R);
+
+/* Cell divergence (eq. 1) of a velocity; r: cell.  If vnorm is not NULL it
+ * receives (host) the volume-weighted norm sqrt(sum V r^2). */
+int lc_divergence(lc_ctx* ctx, const double* v, double* r, double* vnorm);
+
+/* Pressure-correction Poisson solve (Section 3, step 1): (D G) phi = r with the
+ * Neumann wall condition and sum V phi = 0.  r, phi: cell (may alias). */
+int lc_poisson_solve(lc_ctx* ctx, const double* r, double* phi, int precision);
+
+/* Velocity/pressure correction (Section 3, step 2): v = w - G phi on interior
+ * faces (zero on walls) and p = phi.  w, v: velocity; phi, p: cell. */
+int lc_correct(lc_ctx* ctx, const double* w, const double* phi, double* v, double* p);
+
+/* ------------------------------------------------------------- hot path */
+
+/* Divergence-free projection of w by the SIMPLE-like loop of Section 3:
+ * v = w, p = 0; repeat { solve (D G) phi = D v; v -= G phi; p += phi } until
+ * |D v|_V <= tol |D w|_V or max_iter passes.  v_out, p_out may be NULL-free
+ * device buffers (velocity, cell).  stats may be NULL. */
+int lc_project(lc_ctx* ctx, const double* w, double* v_out, double* p_out,
+               int precision, double tol, int max_iter, lc_stats* stats);
+
+/* The next Krylov vector (eqs. 8-10): v_out = P(L_U v_in), p_out its pressure,
+ * by lc_jacobian_apply followed by lc_project. */
+int lc_krylov_vector(lc_ctx* ctx, const double* v_in, double* v_out, double* p_out,
+                     int precision, double tol, int max_iter, lc_stats* stats);
+
+/* Host-only utility (no GPU needed): the modes of one axis used by the
+ * tensor-product Poisson solve.  faces: host array of n+1 strictly increasing
+ * doubles.  Solves K s = lam M s, with M = diag(cell widths) and K the Neumann
+ * couplings 1/(centre distance) across interior faces (the 1D factor of D G).
+ * Outputs (host): lam[n] ascending (the last is the Neumann null mode, ~0),
+ * S[n*n] row-major with the modes as columns (S^T M S = I), Wf[n*n] = S^T M. */
+int lc_axis_modes(int n, const double* faces, double* lam, double* S, double* Wf);
+
+/* ---------------------------------------------------------- vector helpers */
+
+/* Euclidean dot product of two velocity vectors (host result). */
+int lc_dot(lc_ctx* ctx, const double* a, const double* b, double* out);
+
+/* ---------------------------------------------------------------- profiling */
+
+/* Kernel classes timed by the profiling mode. */
+#define LC_K_MOMENTUM 0   /* linearized momentum stencil (eq. 10)             */
+#define LC_K_RESIDUAL 1   /* nonlinear momentum residual                     */
+#define LC_K_DIVERGENCE 2 /* cell divergence + norm partials                 */
+#define LC_K_CORRECT 3    /* velocity/pressure correction                    */
+#define LC_K_TP_X 4       /* tensor-product transform along x                */
+#define LC_K_TP_Y 5       /* tensor-product transform along y                */
+#define LC_K_TP_Z 6       /* tensor-product transform along z                */
+#define LC_K_EIGSCALE 7   /* division by the eigenvalue sums                 */
+#define LC_K_REDUCE 8     /* fixed-order final reductions                    */
+#define LC_K_CAST 9       /* float64 <-> float32 conversions                 */
+#define LC_K_VECTOR 10    /* dot / axpy / scale / fill                       */
+#define LC_K_COUNT 11
+
+/* Enable (1) or disable (0) per-launch HIP-event timing on the context's
+ * stream; enabling clears previous records.  Adds two event records per
+ * kernel launch. */
+int lc_profile_enable(lc_ctx* ctx, int on);
+
+/* Summed device time (ms) and launch count of one kernel class since the last
+ * enable.  Synchronizes the stream. */
+int lc_profile_read(lc_ctx* ctx, int kernel_class, double* total_ms, long* launches);
+
+/* Name of a kernel class (static storage), NULL if out of range. */
+const char* lc_profile_name(int kernel_class);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LIDKRYLOV_H */

@@ -1,0 +1,177 @@
+"""SIMPLE-evaluated Krylov vectors for the lid-driven cube on one MI355X.
+
+Python face of the C ABI in ``include/lidkrylov.h``.  PyTorch supplies device
+memory and the stream; every step runs in the HIP library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+from ._lib import FP64, MIXED, SINE, TANH, UNIFORM, LidKrylovError, Stats  # noqa: F401
+
+__all__ = ["Context", "FP64", "MIXED", "UNIFORM", "SINE", "TANH", "LidKrylovError"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class Context:
+    """One grid, one Reynolds number / lid, one base flow, on one HIP stream."""
+
+    def __init__(self, nx: int, ny: int | None = None, nz: int | None = None, stream=None):
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise RuntimeError("lidkrylov needs a GPU (torch.cuda.is_available() is False)")
+        self.lib = _lib.load()
+        ny = nx if ny is None else ny
+        nz = nx if nz is None else nz
+        self.nx, self.ny, self.nz = nx, ny, nz
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        s = stream if stream is not None else torch.cuda.current_stream()
+        self.stream = s
+        h = C.c_void_p()
+        rc = self.lib.lc_create(C.byref(h), nx, ny, nz, C.c_void_p(s.cuda_stream))
+        if rc != 0:
+            raise LidKrylovError(rc, self.lib.lc_last_error(None).decode())
+        self._h = h
+        self.nvel = int(self.lib.lc_vel_size(h))
+        self.ncell = int(self.lib.lc_cell_size(h))
+
+    # ------------------------------------------------------------- helpers
+    def _check(self, rc, allow_notconv=False):
+        if rc == 0 or (allow_notconv and rc == _lib.LC_ENOTCONV):
+            return rc
+        raise LidKrylovError(rc, self.lib.lc_last_error(self._h).decode())
+
+    def _ptr(self, t, n, name):
+        torch = _torch()
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or t.numel() != n:
+            raise ValueError(f"{name}: need a contiguous float64 CUDA tensor of {n} elements")
+        return C.c_void_p(t.data_ptr())
+
+    def vel(self):
+        return _torch().zeros(self.nvel, dtype=_torch().float64, device=self.device)
+
+    def cells(self):
+        return _torch().zeros(self.ncell, dtype=_torch().float64, device=self.device)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.lib.lc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -------------------------------------------------------------- set-up
+    def set_stretching(self, kind, param=10.0):
+        kinds = {"uniform": UNIFORM, "sine": SINE, "tanh": TANH}
+        k = kinds[kind] if isinstance(kind, str) else int(kind)
+        self._check(self.lib.lc_set_stretching(self._h, k, float(param)))
+
+    def set_grid(self, xf, yf, zf):
+        arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (xf, yf, zf)]
+        for a, n in zip(arrs, (self.nx, self.ny, self.nz)):
+            if a.size != n + 1:
+                raise ValueError("face arrays need n+1 entries")
+        self._check(self.lib.lc_set_grid(self._h, *[a.ctypes.data_as(C.c_void_p) for a in arrs]))
+
+    def get_grid(self):
+        arrs = [np.zeros(n + 1) for n in (self.nx, self.ny, self.nz)]
+        self._check(self.lib.lc_get_grid(self._h, *[a.ctypes.data_as(C.c_void_p) for a in arrs]))
+        return arrs
+
+    def set_re(self, re):
+        self._check(self.lib.lc_set_re(self._h, float(re)))
+
+    def set_lid(self, alpha):
+        self._check(self.lib.lc_set_lid(self._h, float(alpha)))
+
+    def set_base_flow(self, U):
+        self._check(self.lib.lc_set_base_flow(self._h, self._ptr(U, self.nvel, "U")))
+
+    def get_base_flow(self, out=None):
+        out = self.vel() if out is None else out
+        self._check(self.lib.lc_get_base_flow(self._h, self._ptr(out, self.nvel, "U")))
+        return out
+
+    # ------------------------------------------------------------ stencils
+    def jacobian_apply(self, v, out=None):
+        out = self.vel() if out is None else out
+        self._check(self.lib.lc_jacobian_apply(self._h, self._ptr(v, self.nvel, "v"),
+                                               self._ptr(out, self.nvel, "w")))
+        return out
+
+    def residual(self, U, out=None):
+        out = self.vel() if out is None else out
+        self._check(self.lib.lc_residual(self._h, self._ptr(U, self.nvel, "U"),
+                                         self._ptr(out, self.nvel, "R")))
+        return out
+
+    def divergence(self, v, out=None):
+        out = self.cells() if out is None else out
+        nrm = C.c_double()
+        self._check(self.lib.lc_divergence(self._h, self._ptr(v, self.nvel, "v"),
+                                           self._ptr(out, self.ncell, "r"), C.byref(nrm)))
+        return out, nrm.value
+
+    def poisson_solve(self, r, out=None, precision=FP64):
+        out = self.cells() if out is None else out
+        self._check(self.lib.lc_poisson_solve(self._h, self._ptr(r, self.ncell, "r"),
+                                              self._ptr(out, self.ncell, "phi"), int(precision)))
+        return out
+
+    def correct(self, w, phi, v=None, p=None):
+        v = self.vel() if v is None else v
+        p = self.cells() if p is None else p
+        self._check(self.lib.lc_correct(self._h, self._ptr(w, self.nvel, "w"), self._ptr(phi, self.ncell, "phi"),
+                                        self._ptr(v, self.nvel, "v"), self._ptr(p, self.ncell, "p")))
+        return v, p
+
+    # ------------------------------------------------------------ hot path
+    def project(self, w, v=None, p=None, precision=FP64, tol=1e-8, max_iter=8):
+        v = self.vel() if v is None else v
+        p = self.cells() if p is None else p
+        st = Stats()
+        rc = self._check(self.lib.lc_project(self._h, self._ptr(w, self.nvel, "w"), self._ptr(v, self.nvel, "v"),
+                                             self._ptr(p, self.ncell, "p"), int(precision), float(tol),
+                                             int(max_iter), C.byref(st)), allow_notconv=True)
+        return v, p, dict(st.as_dict(), converged=(rc == 0))
+
+    def krylov_vector(self, v_in, v=None, p=None, precision=FP64, tol=1e-8, max_iter=8):
+        v = self.vel() if v is None else v
+        p = self.cells() if p is None else p
+        st = Stats()
+        rc = self._check(self.lib.lc_krylov_vector(self._h, self._ptr(v_in, self.nvel, "v_in"),
+                                                   self._ptr(v, self.nvel, "v"), self._ptr(p, self.ncell, "p"),
+                                                   int(precision), float(tol), int(max_iter), C.byref(st)),
+                         allow_notconv=True)
+        return v, p, dict(st.as_dict(), converged=(rc == 0))
+
+    # ----------------------------------------------------------- profiling
+    def profile(self, on=True):
+        self._check(self.lib.lc_profile_enable(self._h, 1 if on else 0))
+
+    def profile_read(self):
+        """{kernel class: (total ms, launches)} since profiling was enabled."""
+        out = {}
+        for k, name in enumerate(_lib.KERNEL_CLASSES):
+            ms, n = C.c_double(), C.c_long()
+            self._check(self.lib.lc_profile_read(self._h, k, C.byref(ms), C.byref(n)))
+            if n.value:
+                out[name] = (ms.value, n.value)
+        return out
+
+    def dot(self, a, b):
+        out = C.c_double()
+        self._check(self.lib.lc_dot(self._h, self._ptr(a, self.nvel, "a"), self._ptr(b, self.nvel, "b"),
+                                    C.byref(out)))
+        return out.value

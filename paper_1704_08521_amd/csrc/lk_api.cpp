@@ -1,0 +1,600 @@
+// C ABI of lidkrylov: context, grid, stencils, Poisson solve, SIMPLE projection.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/lidkrylov.h"
+#include "lk_internal.h"
+#include "lk_linalg.h"
+
+using namespace lk;
+
+namespace {
+
+std::string g_create_error;
+
+template <typename T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t n = 0;
+};
+
+struct AxisHost {
+  std::vector<double> xf, d, dd, th, rd, rdd;
+  void build(const double* faces, int n) {
+    xf.assign(faces, faces + n + 1);
+    d.resize(n);
+    for (int i = 0; i < n; ++i) d[i] = xf[i + 1] - xf[i];
+    std::vector<double> c(n);
+    for (int i = 0; i < n; ++i) c[i] = 0.5 * (xf[i] + xf[i + 1]);
+    dd.resize(n + 1);
+    dd[0] = 0.5 * d[0];
+    dd[n] = 0.5 * d[n - 1];
+    for (int i = 1; i < n; ++i) dd[i] = c[i] - c[i - 1];
+    th.assign(n + 1, 0.5);
+    for (int i = 1; i < n; ++i) th[i] = d[i - 1] / (2.0 * dd[i]);
+    rd.resize(n);
+    rdd.resize(n + 1);
+    for (int i = 0; i < n; ++i) rd[i] = 1.0 / d[i];
+    for (int i = 0; i <= n; ++i) rdd[i] = 1.0 / dd[i];
+  }
+};
+
+// Tensor-product factorization of one axis, device copies in float64 and float32.
+struct AxisModes {
+  double* lam = nullptr;          // n eigenvalues
+  double *F = nullptr, *Bk = nullptr, *FT = nullptr, *BkT = nullptr;
+  float *F32 = nullptr, *Bk32 = nullptr, *FT32 = nullptr, *BkT32 = nullptr;
+};
+
+}  // namespace
+
+struct lc_ctx {
+  int nx = 0, ny = 0, nz = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  double re = 1.0, alpha = 0.0;
+  bool grid_ready = false;
+  AxisHost ax[3];  // x, y, z
+  double* metric = nullptr;  // device storage of rd, rdd, th, d for the three axes
+  GridDev g{};
+  AxisModes modes[3];
+  void* modes_mem = nullptr;
+  int zero_mode[3] = {0, 0, 0};
+  // fields
+  double* U = nullptr;   // base flow (velocity)
+  double* w = nullptr;   // momentum work vector (velocity)
+  double* r = nullptr;   // divergence (cell)
+  double* phi = nullptr; // correction (cell)
+  double* t1 = nullptr;  // transform temporaries (cell)
+  double* t2 = nullptr;
+  float *r32 = nullptr, *t1_32 = nullptr, *t2_32 = nullptr;
+  double* partials = nullptr;
+  int max_parts = 0;
+  double* dsum = nullptr;   // device scalar
+  double* hsum = nullptr;   // pinned host scalar
+  size_t nvel = 0, ncell = 0;
+  // profiling: event pairs around launches on `stream`
+  struct Rec {
+    int kid;
+    hipEvent_t a, b;
+  };
+  bool prof = false;
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+};
+
+namespace {
+
+int fail(lc_ctx* c, int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  else g_create_error = buf;
+  return code;
+}
+
+#define HIPCHK(c, expr)                                                                       \
+  do {                                                                                        \
+    hipError_t e_ = (expr);                                                                   \
+    if (e_ != hipSuccess) return fail((c), LC_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+hipEvent_t take_event(lc_ctx* c) {
+  if (c->ev_used < c->ev_pool.size()) return c->ev_pool[c->ev_used++];
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  c->ev_pool.push_back(e);
+  c->ev_used++;
+  return e;
+}
+
+// Launch with optional event timing (kernel class `kid`).
+#define KLAUNCH(c, kid, expr)                                                  \
+  do {                                                                         \
+    hipEvent_t a_ = nullptr;                                                   \
+    if ((c)->prof && (a_ = take_event(c))) (void)hipEventRecord(a_, (c)->stream); \
+    HIPCHK(c, expr);                                                           \
+    if ((c)->prof && a_) {                                                     \
+      hipEvent_t b_ = take_event(c);                                           \
+      if (b_) {                                                                \
+        (void)hipEventRecord(b_, (c)->stream);                                 \
+        (c)->recs.push_back({(kid), a_, b_});                                  \
+      }                                                                        \
+    }                                                                          \
+  } while (0)
+
+template <typename T>
+hipError_t dalloc(T** p, size_t n) {
+  return hipMalloc((void**)p, (n ? n : 1) * sizeof(T));
+}
+
+double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+// Fixed-order reduction of partials on the device, then one scalar to the host.
+int reduce_to_host(lc_ctx* c, int nparts, double* out) {
+  KLAUNCH(c, LC_K_REDUCE, launch_sum(c->partials, nparts, c->dsum, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->hsum, c->dsum, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  *out = *c->hsum;
+  return LC_OK;
+}
+
+int vnorm_div(lc_ctx* c, const double* v, double* r, double* out) {
+  int np = 0;
+  KLAUNCH(c, LC_K_DIVERGENCE, launch_divergence(c->g, v, r, c->partials, &np, c->stream));
+  double s2 = 0.0;
+  int rc = reduce_to_host(c, np, &s2);
+  if (rc) return rc;
+  *out = std::sqrt(s2);
+  return LC_OK;
+}
+
+int upload_grid(lc_ctx* c) {
+  const int n[3] = {c->nx, c->ny, c->nz};
+  // metrics: per axis rd (n), rdd (n+1), th (n+1), d (n)
+  size_t total = 0;
+  for (int a = 0; a < 3; ++a) total += 4 * (size_t)n[a] + 2;
+  if (!c->metric) HIPCHK(c, dalloc(&c->metric, total));
+  std::vector<double> host(total);
+  size_t off = 0;
+  AxisDev* dst[3] = {&c->g.x, &c->g.y, &c->g.z};
+  for (int a = 0; a < 3; ++a) {
+    const AxisHost& A = c->ax[a];
+    double* base = c->metric + off;
+    std::copy(A.rd.begin(), A.rd.end(), host.begin() + off);
+    dst[a]->rd = base;
+    off += n[a];
+    std::copy(A.rdd.begin(), A.rdd.end(), host.begin() + off);
+    dst[a]->rdd = c->metric + off;
+    off += n[a] + 1;
+    std::copy(A.th.begin(), A.th.end(), host.begin() + off);
+    dst[a]->th = c->metric + off;
+    off += n[a] + 1;
+    std::copy(A.d.begin(), A.d.end(), host.begin() + off);
+    dst[a]->d = c->metric + off;
+    off += n[a];
+    dst[a]->n = n[a];
+  }
+  HIPCHK(c, hipMemcpyAsync(c->metric, host.data(), total * sizeof(double), hipMemcpyHostToDevice, c->stream));
+
+  // tensor-product factorization of each axis
+  size_t mbytes = 0;
+  for (int a = 0; a < 3; ++a) {
+    const size_t nn = (size_t)n[a] * n[a];
+    mbytes += n[a] * sizeof(double) + 4 * nn * sizeof(double) + 4 * nn * sizeof(float);
+  }
+  if (!c->modes_mem) HIPCHK(c, hipMalloc(&c->modes_mem, mbytes));
+  std::vector<char> mhost(mbytes);
+  char* hp = mhost.data();
+  char* dp = (char*)c->modes_mem;
+  for (int a = 0; a < 3; ++a) {
+    const int m = n[a];
+    const size_t nn = (size_t)m * m;
+    std::vector<double> lam, S, Wf;
+    if (!neumann_modes(m, c->ax[a].d.data(), c->ax[a].dd.data(), lam, S, Wf))
+      return fail(c, LC_EINVAL, "tridiagonal eigen-solver did not converge on axis %d", a);
+    c->zero_mode[a] = m - 1;  // ascending; the Neumann null mode is the largest (~0)
+    std::vector<double> F(Wf), Bk(S), FT(nn), BkT(nn);
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j) {
+        FT[(size_t)j * m + i] = F[(size_t)i * m + j];
+        BkT[(size_t)j * m + i] = Bk[(size_t)i * m + j];
+      }
+    AxisModes& M = c->modes[a];
+    auto put_d = [&](const std::vector<double>& v, double** dptr) {
+      std::memcpy(hp, v.data(), v.size() * sizeof(double));
+      *dptr = (double*)dp;
+      hp += v.size() * sizeof(double);
+      dp += v.size() * sizeof(double);
+    };
+    auto put_f = [&](const std::vector<double>& v, float** dptr) {
+      for (size_t q = 0; q < v.size(); ++q) ((float*)hp)[q] = (float)v[q];
+      *dptr = (float*)dp;
+      hp += v.size() * sizeof(float);
+      dp += v.size() * sizeof(float);
+    };
+    put_d(lam, &M.lam);
+    put_d(F, &M.F);
+    put_d(Bk, &M.Bk);
+    put_d(FT, &M.FT);
+    put_d(BkT, &M.BkT);
+    put_f(F, &M.F32);
+    put_f(Bk, &M.Bk32);
+    put_f(FT, &M.FT32);
+    put_f(BkT, &M.BkT32);
+  }
+  HIPCHK(c, hipMemcpyAsync(c->modes_mem, mhost.data(), mbytes, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->grid_ready = true;
+  return LC_OK;
+}
+
+// (D G) phi = r by transforming with S^T M along x, y, z, dividing by the sums of
+// the axis eigenvalues (constant mode set to zero) and transforming back with S.
+template <typename T>
+int tp_solve(lc_ctx* c, const T* r, T* phi, T* t1, T* t2) {
+  const int nx = c->nx, ny = c->ny, nz = c->nz;
+  const long pl = (long)nx * ny;
+  auto pick = [](const AxisModes& M, int which) -> const T* {
+    if constexpr (sizeof(T) == sizeof(double)) {
+      const double* a[4] = {M.F, M.Bk, M.FT, M.BkT};
+      return (const T*)a[which];
+    } else {
+      const float* a[4] = {M.F32, M.Bk32, M.FT32, M.BkT32};
+      return (const T*)a[which];
+    }
+  };
+  const AxisModes &X = c->modes[0], &Y = c->modes[1], &Z = c->modes[2];
+  hipStream_t s = c->stream;
+  // forward: x (contract the contiguous index), y (per z-plane), z
+  KLAUNCH(c, LC_K_TP_X, launch_gemm<T>(ny * nz, nx, nx, r, nx, 0, pick(X, 2), nx, 0, t1, nx, 0, 1, s));
+  KLAUNCH(c, LC_K_TP_Y, launch_gemm<T>(ny, nx, ny, pick(Y, 0), ny, 0, t1, nx, pl, t2, nx, pl, nz, s));
+  KLAUNCH(c, LC_K_TP_Z, launch_gemm<T>(nz, (int)pl, nz, pick(Z, 0), nz, 0, t2, pl, 0, t1, pl, 0, 1, s));
+  KLAUNCH(c, LC_K_EIGSCALE, launch_eigscale<T>(t1, X.lam, Y.lam, Z.lam, nx, ny, nz, c->zero_mode[0], c->zero_mode[1],
+                               c->zero_mode[2], s));
+  // backward: z, y, x
+  KLAUNCH(c, LC_K_TP_Z, launch_gemm<T>(nz, (int)pl, nz, pick(Z, 1), nz, 0, t1, pl, 0, t2, pl, 0, 1, s));
+  KLAUNCH(c, LC_K_TP_Y, launch_gemm<T>(ny, nx, ny, pick(Y, 1), ny, 0, t2, nx, pl, t1, nx, pl, nz, s));
+  KLAUNCH(c, LC_K_TP_X, launch_gemm<T>(ny * nz, nx, nx, t1, nx, 0, pick(X, 3), nx, 0, phi, nx, 0, 1, s));
+  return LC_OK;
+}
+
+int poisson(lc_ctx* c, const double* r, double* phi, int precision) {
+  if (precision == LC_FP64) return tp_solve<double>(c, r, phi, c->t1, c->t2);
+  KLAUNCH(c, LC_K_CAST, launch_d2f(c->ncell, r, c->r32, c->stream));
+  int rc = tp_solve<float>(c, c->r32, c->r32, c->t1_32, c->t2_32);
+  if (rc) return rc;
+  KLAUNCH(c, LC_K_CAST, launch_f2d(c->ncell, c->r32, phi, false, c->stream));
+  return LC_OK;
+}
+
+int check_ready(lc_ctx* c) {
+  if (!c) return LC_EINVAL;
+  if (!c->grid_ready) return fail(c, LC_ESTATE, "grid not set");
+  return LC_OK;
+}
+
+bool aligned(const void* p) { return p && ((uintptr_t)p % 8 == 0); }
+
+}  // namespace
+
+extern "C" {
+
+const char* lc_version(void) { return "lidkrylov 0.1 (gfx950)"; }
+
+const char* lc_last_error(const lc_ctx* c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+
+size_t lc_vel_size(const lc_ctx* c) { return c ? c->nvel : 0; }
+size_t lc_cell_size(const lc_ctx* c) { return c ? c->ncell : 0; }
+
+int lc_create(lc_ctx** out, int nx, int ny, int nz, void* hip_stream) {
+  if (!out) return fail(nullptr, LC_EINVAL, "null output pointer");
+  *out = nullptr;
+  if (nx < 2 || ny < 2 || nz < 2 || nx > 4096 || ny > 4096 || nz > 4096)
+    return fail(nullptr, LC_EINVAL, "grid size %dx%dx%d outside [2, 4096]", nx, ny, nz);
+  lc_ctx* c = new lc_ctx();
+  c->nx = nx;
+  c->ny = ny;
+  c->nz = nz;
+  c->stream = (hipStream_t)hip_stream;
+  c->nvel = vel_layout(nx, ny, nz).total();
+  c->ncell = (size_t)nx * ny * nz;
+  c->max_parts = (int)((c->ncell + kReduceBlock - 1) / kReduceBlock) + 4096;
+  bool ok = dalloc(&c->U, c->nvel) == hipSuccess && dalloc(&c->w, c->nvel) == hipSuccess &&
+            dalloc(&c->r, c->ncell) == hipSuccess && dalloc(&c->phi, c->ncell) == hipSuccess &&
+            dalloc(&c->t1, c->ncell) == hipSuccess && dalloc(&c->t2, c->ncell) == hipSuccess &&
+            dalloc(&c->r32, c->ncell) == hipSuccess && dalloc(&c->t1_32, c->ncell) == hipSuccess &&
+            dalloc(&c->t2_32, c->ncell) == hipSuccess && dalloc(&c->partials, c->max_parts) == hipSuccess &&
+            dalloc(&c->dsum, 1) == hipSuccess &&
+            hipHostMalloc((void**)&c->hsum, sizeof(double), hipHostMallocDefault) == hipSuccess;
+  if (!ok) {
+    lc_destroy(c);
+    return fail(nullptr, LC_ENOMEM, "device allocation failed for %dx%dx%d", nx, ny, nz);
+  }
+  if (hipMemsetAsync(c->U, 0, c->nvel * sizeof(double), c->stream) != hipSuccess) {
+    lc_destroy(c);
+    return fail(nullptr, LC_EHIP, "hipMemsetAsync failed");
+  }
+  int rc = lc_set_stretching(c, LC_UNIFORM, 0.0);
+  if (rc) {
+    g_create_error = c->err;
+    lc_destroy(c);
+    return rc;
+  }
+  *out = c;
+  return LC_OK;
+}
+
+int lc_destroy(lc_ctx* c) {
+  if (!c) return LC_OK;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  else (void)hipDeviceSynchronize();
+  void* ptrs[] = {c->U, c->w, c->r, c->phi, c->t1, c->t2, c->r32, c->t1_32, c->t2_32, c->partials,
+                  c->dsum, c->metric, c->modes_mem};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  if (c->hsum) (void)hipHostFree(c->hsum);
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  delete c;
+  return LC_OK;
+}
+
+int lc_set_stream(lc_ctx* c, void* s) {
+  if (!c) return LC_EINVAL;
+  c->stream = (hipStream_t)s;
+  return LC_OK;
+}
+
+int lc_set_grid(lc_ctx* c, const double* xf, const double* yf, const double* zf) {
+  if (!c || !xf || !yf || !zf) return fail(c, LC_EINVAL, "null argument");
+  const double* f[3] = {xf, yf, zf};
+  const int n[3] = {c->nx, c->ny, c->nz};
+  for (int a = 0; a < 3; ++a) {
+    if (f[a][0] != 0.0 || f[a][n[a]] != 1.0) return fail(c, LC_EINVAL, "axis %d faces must run from 0 to 1", a);
+    for (int i = 0; i < n[a]; ++i)
+      if (!(f[a][i + 1] > f[a][i]) || !std::isfinite(f[a][i + 1]))
+        return fail(c, LC_EINVAL, "axis %d faces must increase strictly", a);
+  }
+  for (int a = 0; a < 3; ++a) c->ax[a].build(f[a], n[a]);
+  return upload_grid(c);
+}
+
+int lc_set_stretching(lc_ctx* c, int kind, double param) {
+  if (!c) return LC_EINVAL;
+  if (kind == LC_TANH && !(param > 1.0)) return fail(c, LC_EINVAL, "tanh ratio must exceed 1");
+  if (kind != LC_UNIFORM && kind != LC_SINE && kind != LC_TANH) return fail(c, LC_EINVAL, "unknown stretching");
+  const int n[3] = {c->nx, c->ny, c->nz};
+  std::vector<double> f[3];
+  for (int a = 0; a < 3; ++a) {
+    f[a].resize(n[a] + 1);
+    for (int i = 0; i <= n[a]; ++i) {
+      const double xi = (double)i / n[a];
+      double x = xi;
+      if (kind == LC_SINE) {
+        x = xi - 0.0975 * std::sin(2.0 * M_PI * xi);  // Section 3, eq. 5
+      } else if (kind == LC_TANH) {
+        const double b = std::acosh(std::sqrt(param));
+        x = 0.5 * (1.0 + std::tanh(b * (2.0 * xi - 1.0)) / std::tanh(b));
+      }
+      f[a][i] = x;
+    }
+    f[a][0] = 0.0;
+    f[a][n[a]] = 1.0;
+  }
+  return lc_set_grid(c, f[0].data(), f[1].data(), f[2].data());
+}
+
+int lc_get_grid(const lc_ctx* c, double* xf, double* yf, double* zf) {
+  if (!c || !xf || !yf || !zf) return LC_EINVAL;
+  std::copy(c->ax[0].xf.begin(), c->ax[0].xf.end(), xf);
+  std::copy(c->ax[1].xf.begin(), c->ax[1].xf.end(), yf);
+  std::copy(c->ax[2].xf.begin(), c->ax[2].xf.end(), zf);
+  return LC_OK;
+}
+
+int lc_set_re(lc_ctx* c, double re) {
+  if (!c) return LC_EINVAL;
+  if (!(re > 0.0) || !std::isfinite(re)) return fail(c, LC_EINVAL, "Re must be positive and finite");
+  c->re = re;
+  return LC_OK;
+}
+
+int lc_set_lid(lc_ctx* c, double alpha) {
+  if (!c) return LC_EINVAL;
+  if (!std::isfinite(alpha)) return fail(c, LC_EINVAL, "lid angle must be finite");
+  c->alpha = alpha;
+  return LC_OK;
+}
+
+int lc_set_base_flow(lc_ctx* c, const double* U) {
+  if (!c || !aligned(U)) return fail(c, LC_EINVAL, "null or misaligned base flow");
+  HIPCHK(c, hipMemcpyAsync(c->U, U, c->nvel * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  KLAUNCH(c, LC_K_VECTOR, launch_zero_walls(c->U, c->nx, c->ny, c->nz, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return LC_OK;
+}
+
+int lc_get_base_flow(const lc_ctx* c, double* U) {
+  if (!c || !aligned(U)) return LC_EINVAL;
+  lc_ctx* m = const_cast<lc_ctx*>(c);
+  HIPCHK(m, hipMemcpyAsync(U, c->U, c->nvel * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(m, hipStreamSynchronize(c->stream));
+  return LC_OK;
+}
+
+int lc_jacobian_apply(lc_ctx* c, const double* v, double* w) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  if (!aligned(v) || !aligned(w) || v == w) return fail(c, LC_EINVAL, "bad or aliased velocity pointers");
+  KLAUNCH(c, LC_K_MOMENTUM, launch_momentum(c->g, c->U, v, w, 1.0 / c->re, 1.0, false, 0, 0, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return LC_OK;
+}
+
+int lc_residual(lc_ctx* c, const double* U, double* R) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  if (!aligned(U) || !aligned(R) || U == R) return fail(c, LC_EINVAL, "bad or aliased velocity pointers");
+  KLAUNCH(c, LC_K_RESIDUAL, launch_momentum(c->g, U, U, R, 1.0 / c->re, 0.5, true, std::cos(c->alpha), std::sin(c->alpha),
+                            c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return LC_OK;
+}
+
+int lc_divergence(lc_ctx* c, const double* v, double* r, double* vn) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  if (!aligned(v) || !aligned(r)) return fail(c, LC_EINVAL, "bad pointers");
+  double nrm = 0.0;
+  rc = vnorm_div(c, v, r, &nrm);
+  if (rc) return rc;
+  if (vn) *vn = nrm;
+  return LC_OK;
+}
+
+int lc_poisson_solve(lc_ctx* c, const double* r, double* phi, int precision) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  if (!aligned(r) || !aligned(phi)) return fail(c, LC_EINVAL, "bad pointers");
+  if (precision != LC_FP64 && precision != LC_MIXED) return fail(c, LC_EINVAL, "unknown precision");
+  rc = poisson(c, r, phi, precision);
+  if (rc) return rc;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return LC_OK;
+}
+
+int lc_correct(lc_ctx* c, const double* w, const double* phi, double* v, double* p) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  if (!aligned(w) || !aligned(phi) || !aligned(v) || (p && !aligned(p)) || v == w)
+    return fail(c, LC_EINVAL, "bad pointers");
+  KLAUNCH(c, LC_K_CORRECT, launch_correct(c->g, w, phi, v, p, false, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return LC_OK;
+}
+
+int lc_project(lc_ctx* c, const double* w, double* v, double* p, int precision, double tol, int max_iter,
+               lc_stats* st) {
+  const double t0 = now_ms();
+  int rc = check_ready(c);
+  if (rc) return rc;
+  if (!aligned(w) || !aligned(v) || !aligned(p) || v == w) return fail(c, LC_EINVAL, "bad pointers");
+  if (precision != LC_FP64 && precision != LC_MIXED) return fail(c, LC_EINVAL, "unknown precision");
+  if (!(tol >= 0.0) || max_iter < 1) return fail(c, LC_EINVAL, "bad tolerance or iteration cap");
+  lc_stats local{};
+  lc_stats& S = st ? *st : local;
+  std::memset(&S, 0, sizeof S);
+  double n0 = 0.0;
+  rc = vnorm_div(c, w, c->r, &n0);
+  if (rc) return rc;
+  if (!std::isfinite(n0)) return fail(c, LC_EINVAL, "non-finite input");
+  S.rho0 = n0;
+  if (n0 == 0.0) {
+    // already divergence-free: v = w (walls zeroed), p = 0
+    HIPCHK(c, hipMemsetAsync(c->phi, 0, c->ncell * sizeof(double), c->stream));
+    KLAUNCH(c, LC_K_CORRECT, launch_correct(c->g, w, c->phi, v, p, false, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    S.ms_total = now_ms() - t0;
+    return LC_OK;
+  }
+  // SIMPLE loop (Section 3): v = w, p = 0; repeat {solve; v -= G phi; p += phi}
+  for (int it = 0; it < max_iter; ++it) {
+    rc = poisson(c, c->r, c->phi, precision);
+    if (rc) return rc;
+    KLAUNCH(c, LC_K_CORRECT, launch_correct(c->g, w, c->phi, v, p, it > 0, c->stream));
+    double nk = 0.0;
+    rc = vnorm_div(c, v, c->r, &nk);
+    if (rc) return rc;
+    S.iterations = it + 1;
+    S.rho = nk / n0;
+    if (it < 16) S.rho_hist[it] = S.rho;
+    if (!std::isfinite(S.rho)) return fail(c, LC_EINVAL, "non-finite divergence during projection");
+    if (S.rho <= tol) {
+      S.ms_total = now_ms() - t0;
+      return LC_OK;
+    }
+  }
+  S.ms_total = now_ms() - t0;
+  return LC_ENOTCONV;
+}
+
+int lc_krylov_vector(lc_ctx* c, const double* vin, double* vout, double* pout, int precision, double tol,
+                     int max_iter, lc_stats* st) {
+  const double t0 = now_ms();
+  int rc = check_ready(c);
+  if (rc) return rc;
+  if (!aligned(vin) || !aligned(vout) || vin == vout) return fail(c, LC_EINVAL, "bad or aliased pointers");
+  KLAUNCH(c, LC_K_MOMENTUM, launch_momentum(c->g, c->U, vin, c->w, 1.0 / c->re, 1.0, false, 0, 0, c->stream));
+  rc = lc_project(c, c->w, vout, pout, precision, tol, max_iter, st);
+  if (st) st->ms_total = now_ms() - t0;
+  return rc;
+}
+
+int lc_dot(lc_ctx* c, const double* a, const double* b, double* out) {
+  if (!c || !aligned(a) || !aligned(b) || !out) return fail(c, LC_EINVAL, "bad pointers");
+  int np = 0;
+  KLAUNCH(c, LC_K_VECTOR, launch_dot_partials(a, b, c->nvel, c->partials, &np, c->stream));
+  return reduce_to_host(c, np, out);
+}
+
+}  // extern "C"
+
+static const char* kKernelNames[LC_K_COUNT] = {"momentum", "residual", "divergence", "correct",
+                                                "tp_x",     "tp_y",     "tp_z",       "eigscale",
+                                                "reduce",   "cast",     "vector"};
+
+extern "C" const char* lc_profile_name(int k) { return (k >= 0 && k < LC_K_COUNT) ? kKernelNames[k] : nullptr; }
+
+extern "C" int lc_profile_enable(lc_ctx* c, int on) {
+  if (!c) return LC_EINVAL;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->recs.clear();
+  c->ev_used = 0;
+  c->prof = on != 0;
+  return LC_OK;
+}
+
+extern "C" int lc_profile_read(lc_ctx* c, int k, double* total_ms, long* launches) {
+  if (!c || k < 0 || k >= LC_K_COUNT || !total_ms || !launches) return LC_EINVAL;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  double t = 0.0;
+  long n = 0;
+  for (const auto& r : c->recs) {
+    if (r.kid != k) continue;
+    float ms = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&ms, r.a, r.b));
+    t += ms;
+    ++n;
+  }
+  *total_ms = t;
+  *launches = n;
+  return LC_OK;
+}
+
+extern "C" int lc_axis_modes(int n, const double* faces, double* lam, double* S, double* Wf) {
+  if (n < 1 || !faces || !lam || !S || !Wf) return LC_EINVAL;
+  for (int i = 0; i < n; ++i)
+    if (!(faces[i + 1] > faces[i])) return LC_EINVAL;
+  AxisHost A;
+  A.build(faces, n);
+  std::vector<double> l, s, w;
+  if (!neumann_modes(n, A.d.data(), A.dd.data(), l, s, w)) return LC_EINVAL;
+  std::copy(l.begin(), l.end(), lam);
+  std::copy(s.begin(), s.end(), S);
+  std::copy(w.begin(), w.end(), Wf);
+  return LC_OK;
+}

@@ -1,0 +1,97 @@
+// Internal declarations shared by the kernel file and the host API.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace lk {
+
+// One axis of the stretched staggered grid, device arrays.
+//   d[n]    cell widths             rd[n]  = 1/d
+//   dd[n+1] centre distances across faces (half widths at the walls), rdd = 1/dd
+//   th[n+1] interpolation weight of face i between centres i-1 and i
+struct AxisDev {
+  const double* rd;
+  const double* rdd;
+  const double* th;
+  const double* d;
+  int n;
+};
+
+struct GridDev {
+  AxisDev x, y, z;
+};
+
+// Offsets of u, v, w inside a packed velocity.
+struct VelLayout {
+  size_t nu, nv, nw;  // element counts
+  size_t ou() const { return 0; }
+  size_t ov() const { return nu; }
+  size_t ow() const { return nu + nv; }
+  size_t total() const { return nu + nv + nw; }
+};
+
+inline VelLayout vel_layout(int nx, int ny, int nz) {
+  VelLayout L;
+  L.nu = (size_t)(nx + 1) * ny * nz;
+  L.nv = (size_t)nx * (ny + 1) * nz;
+  L.nw = (size_t)nx * ny * (nz + 1);
+  return L;
+}
+
+// ------------------------------------------------------------ launchers
+// All launchers enqueue on `s` and return the launch status.
+
+// out = rre * Lap_g(b) - s * [C(a, b) + C(b, a)], lid only if `lid` is set.
+// Jacobian: a = U, b = v, s = 1, lid off.  Residual: a = b = U, s = 1/2, lid on.
+hipError_t launch_momentum(const GridDev& g, const double* a, const double* b, double* out,
+                           double rre, double s, bool lid, double lid_u, double lid_v,
+                           hipStream_t st);
+
+// r = D v (cell), and per-block partial sums of V r^2 into `partials`
+// (nblocks returned through *nparts; partials may be null).
+hipError_t launch_divergence(const GridDev& g, const double* v, double* r, double* partials,
+                             int* nparts, hipStream_t st);
+
+// v = w - G phi (interior faces), zero on walls; p = phi if p != null.
+// If accumulate: v -= G phi in place on v (w ignored) and p += phi.
+hipError_t launch_correct(const GridDev& g, const double* w, const double* phi, double* v,
+                          double* p, bool accumulate, hipStream_t st);
+
+// Fixed-order sum of n partials into out[0] (one block).
+hipError_t launch_sum(const double* partials, int n, double* out, hipStream_t st);
+
+// Per-block partial dot products of two arrays of length n.
+hipError_t launch_dot_partials(const double* a, const double* b, size_t n, double* partials,
+                               int* nparts, hipStream_t st);
+
+// y = a*x + y ; x *= a ; y = x
+hipError_t launch_axpy(size_t n, double a, const double* x, double* y, hipStream_t st);
+hipError_t launch_scale(size_t n, double a, double* x, hipStream_t st);
+
+// Batched row-major GEMM: C[b] = A[b] * B[b], A: MxK, B: KxN, C: MxN.
+template <typename T>
+hipError_t launch_gemm(int M, int N, int K, const T* A, long lda, long sA, const T* B, long ldb,
+                       long sB, T* C, long ldc, long sC, int batch, hipStream_t st);
+
+// x[k][j][i] *= inv(lz[k] + ly[j] + lx[i]) with the (zk, zj, zi) mode set to 0.
+template <typename T>
+hipError_t launch_eigscale(T* x, const double* lx, const double* ly, const double* lz, int nx,
+                           int ny, int nz, int zi, int zj, int zk, hipStream_t st);
+
+// Precision casts.
+hipError_t launch_d2f(size_t n, const double* in, float* out, hipStream_t st);
+// out = in (float -> double), or out += in when accumulate
+hipError_t launch_f2d(size_t n, const float* in, double* out, bool accumulate, hipStream_t st);
+
+// Fill with the counter-based SplitMix64 uniform [-1, 1) stream `seed`.
+hipError_t launch_uniform(double* x, size_t n, uint64_t seed, hipStream_t st);
+
+// Zero the wall-normal faces of a packed velocity.
+hipError_t launch_zero_walls(double* vel, int nx, int ny, int nz, hipStream_t st);
+
+constexpr int kReduceBlock = 256;
+
+}  // namespace lk

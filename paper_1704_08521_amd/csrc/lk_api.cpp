@@ -260,16 +260,19 @@ int tp_solve(lc_ctx* c, const T* r, T* phi, T* t1, T* t2) {
   };
   const AxisModes &X = c->modes[0], &Y = c->modes[1], &Z = c->modes[2];
   hipStream_t s = c->stream;
-  // forward: x (contract the contiguous index), y (per z-plane), z
-  KLAUNCH(c, LC_K_TP_X, launch_gemm<T>(ny * nz, nx, nx, r, nx, 0, pick(X, 2), nx, 0, t1, nx, 0, 1, s));
-  KLAUNCH(c, LC_K_TP_Y, launch_gemm<T>(ny, nx, ny, pick(Y, 0), ny, 0, t1, nx, pl, t2, nx, pl, nz, s));
-  KLAUNCH(c, LC_K_TP_Z, launch_gemm<T>(nz, (int)pl, nz, pick(Z, 0), nz, 0, t2, pl, 0, t1, pl, 0, 1, s));
-  KLAUNCH(c, LC_K_EIGSCALE, launch_eigscale<T>(t1, X.lam, Y.lam, Z.lam, nx, ny, nz, c->zero_mode[0], c->zero_mode[1],
-                               c->zero_mode[2], s));
+  const int n_yz = ny * nz, n_xz = nx * nz;
+  const double* nul = nullptr;
+  // forward: x (contiguous lines), y (columns (k, i), rows nx apart), z (rows nx*ny apart),
+  // the division by lam_x + lam_y + lam_z fused into the z transform
+  KLAUNCH(c, LC_K_TP_X, launch_tp_right<T>(n_yz, nx, nx, r, pick(X, 2), t1, s));
+  KLAUNCH(c, LC_K_TP_Y, launch_tp_left<T>(ny, n_xz, ny, pick(Y, 0), t1, t2, nx, pl, nx, nul, nul, nul, 1, 0, 0, 0, s));
+  KLAUNCH(c, LC_K_TP_Z, launch_tp_left<T>(nz, (int)pl, nz, pick(Z, 0), t2, t1, (int)pl, 0, pl, Z.lam, Y.lam, X.lam,
+                                          nx, c->zero_mode[2], c->zero_mode[1], c->zero_mode[0], s));
   // backward: z, y, x
-  KLAUNCH(c, LC_K_TP_Z, launch_gemm<T>(nz, (int)pl, nz, pick(Z, 1), nz, 0, t1, pl, 0, t2, pl, 0, 1, s));
-  KLAUNCH(c, LC_K_TP_Y, launch_gemm<T>(ny, nx, ny, pick(Y, 1), ny, 0, t2, nx, pl, t1, nx, pl, nz, s));
-  KLAUNCH(c, LC_K_TP_X, launch_gemm<T>(ny * nz, nx, nx, t1, nx, 0, pick(X, 3), nx, 0, phi, nx, 0, 1, s));
+  KLAUNCH(c, LC_K_TP_Z, launch_tp_left<T>(nz, (int)pl, nz, pick(Z, 1), t1, t2, (int)pl, 0, pl, nul, nul, nul, 1, 0, 0,
+                                          0, s));
+  KLAUNCH(c, LC_K_TP_Y, launch_tp_left<T>(ny, n_xz, ny, pick(Y, 1), t2, t1, nx, pl, nx, nul, nul, nul, 1, 0, 0, 0, s));
+  KLAUNCH(c, LC_K_TP_X, launch_tp_right<T>(n_yz, nx, nx, t1, pick(X, 3), phi, s));
   return LC_OK;
 }
 

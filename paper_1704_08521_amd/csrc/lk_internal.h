@@ -71,15 +71,18 @@ hipError_t launch_dot_partials(const double* a, const double* b, size_t n, doubl
 hipError_t launch_axpy(size_t n, double a, const double* x, double* y, hipStream_t st);
 hipError_t launch_scale(size_t n, double a, double* x, hipStream_t st);
 
-// Batched row-major GEMM: C[b] = A[b] * B[b], A: MxK, B: KxN, C: MxN.
+// Tensor-product line transform along a strided axis: C[m][n] = sum_k A[m][k] B[k][n]
+// with A the K x K (= M x K) mode matrix and B/C data whose column n starts at
+// (n / nseg) * seg_stride + n % nseg with rows kstride apart.  If lm is set the
+// result is divided by lm[m] + ly[n / nxs] + lx[n % nxs] (mode (zm, zj, zi) -> 0).
 template <typename T>
-hipError_t launch_gemm(int M, int N, int K, const T* A, long lda, long sA, const T* B, long ldb,
-                       long sB, T* C, long ldc, long sC, int batch, hipStream_t st);
+hipError_t launch_tp_left(int M, int N, int K, const T* A, const T* B, T* C, int nseg, long seg_stride,
+                          long kstride, const double* lm, const double* ly, const double* lx, int nxs, int zm,
+                          int zj, int zi, hipStream_t st);
 
-// x[k][j][i] *= inv(lz[k] + ly[j] + lx[i]) with the (zk, zj, zi) mode set to 0.
+// Line transform along the contiguous axis: C (M x N) = A (M x K data) * B (K x N).
 template <typename T>
-hipError_t launch_eigscale(T* x, const double* lx, const double* ly, const double* lz, int nx,
-                           int ny, int nz, int zi, int zj, int zk, hipStream_t st);
+hipError_t launch_tp_right(int M, int N, int K, const T* A, const T* B, T* C, hipStream_t st);
 
 // Precision casts.
 hipError_t launch_d2f(size_t n, const double* in, float* out, hipStream_t st);

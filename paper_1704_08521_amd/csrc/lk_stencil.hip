@@ -1,0 +1,378 @@
+// Staggered finite-volume stencils: linearized momentum / residual (eq. 10,
+// eq. 2), cell divergence (eq. 1) and the projection correction (Section 3,
+// step 2).
+#include <hip/hip_runtime.h>
+
+#include "lk_device.h"
+
+namespace lk {
+namespace {
+
+// ------------------------------------------------------------------ momentum
+// One block owns a TX x TY column of (i, j) positions and marches along z over
+// a chunk of planes.  For each of the six input fields (advecting a = U and
+// advected b, components u, v, w) a ring of three planes k-1, k, k+1 with a
+// one-cell x/y halo lives in LDS.  Positions outside a field's stored range are
+// filled with the wall value of that position: 0 on wall-normal faces, beyond
+// tangential walls 0 or, for the advected field of the nonlinear residual, the
+// lid velocity at z = 1 (eq. 4).  With these ghosts the wall fluxes of the
+// Laplacian ((first - wall)/half width) and the vanishing edge fluxes on walls
+// follow from the interior formulas, so the compute has no wall branches.
+constexpr int MTX = 64, MTY = 4;
+constexpr int MPX = MTX + 2, MPY = MTY + 2, MPS = MPX * MPY;
+
+// Value of component `comp` at (k, j, i) with the ghost rule above.  Branch
+// free: the load is unconditional from an in-range offset (0 for ghosts) and the
+// ghost is selected afterwards, so a thread's loads all issue back to back.
+template <bool LID>
+__device__ __forceinline__ double tap_load(const double* __restrict__ p, int comp, bool adv, int nx, int ny, int nz,
+                                           int k, int j, int i, double lid_u, double lid_v) {
+  bool ok, tang;
+  long off;
+  double lid;
+  if (comp == 0) {  // u: i in [0, nx] (walls at 0, nx), j < ny, k < nz
+    tang = (i > 0) & (i < nx) & (j >= 0) & (j < ny);
+    ok = tang & (k >= 0) & (k < nz);
+    off = ((long)k * ny + j) * (nx + 1) + i;
+    lid = lid_u;
+  } else if (comp == 1) {  // v: j in [0, ny] (walls), i < nx, k < nz
+    tang = (j > 0) & (j < ny) & (i >= 0) & (i < nx);
+    ok = tang & (k >= 0) & (k < nz);
+    off = ((long)k * (ny + 1) + j) * nx + i;
+    lid = lid_v;
+  } else {  // w: k in [0, nz] (walls), i < nx, j < ny
+    tang = false;
+    ok = (k > 0) & (k < nz) & (i >= 0) & (i < nx) & (j >= 0) & (j < ny);
+    off = ((long)k * ny + j) * nx + i;
+    lid = 0.0;
+  }
+  const double x = p[ok ? off : 0];
+  const double ghost = (LID && !adv && tang && k == nz) ? lid : 0.0;
+  return ok ? x : ghost;
+}
+
+template <bool LID>
+__global__ void __launch_bounds__(MTX* MTY) k_momentum(GridDev g, const double* __restrict__ a,
+                                                      const double* __restrict__ b, double* __restrict__ out,
+                                                      double rre, double s, double lid_u, double lid_v, int kchunk) {
+  __shared__ double sm[6][3][MPS];  // 0..2: a (u, v, w); 3..5: b (u, v, w)
+  const int nx = g.x.n, ny = g.y.n, nz = g.z.n;
+  const size_t nu = (size_t)(nx + 1) * ny * nz, nv = (size_t)nx * (ny + 1) * nz;
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * MTX + tx;
+  const int i0 = blockIdx.x * MTX, j0 = blockIdx.y * MTY;
+  const int kb = blockIdx.z * kchunk;
+  const int ke = min(kb + kchunk, nz + 1);
+  const int i = i0 + tx, j = j0 + ty;
+  const double* src[6] = {a, a + nu, a + nu + nv, b, b + nu, b + nu + nv};
+
+  // Plane loads go to registers first (all issued back to back from in-range
+  // addresses, ghosts selected afterwards) and are written to LDS one step later,
+  // so the next plane is in flight while the current one is computed.
+  constexpr int NT = MTX * MTY;
+  constexpr int PER = (MPS + NT - 1) / NT;
+  double reg[6][PER];
+  auto load = [&](int k) {
+#pragma unroll
+    for (int arr = 0; arr < 6; ++arr) {
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int e = min(tid + q * NT, MPS - 1);  // the surplus threads re-read the last entry
+        const int yy = e / MPX, xx = e - yy * MPX;
+        reg[arr][q] = tap_load<LID>(src[arr], arr % 3, arr < 3, nx, ny, nz, k, j0 - 1 + yy, i0 - 1 + xx, lid_u,
+                                    lid_v);
+      }
+    }
+  };
+  auto store = [&](int k) {
+    const int slot = (k + 3) % 3;
+#pragma unroll
+    for (int arr = 0; arr < 6; ++arr) {
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int e = tid + q * NT;
+        if (e < MPS) sm[arr][slot][e] = reg[arr][q];
+      }
+    }
+  };
+
+  // per-thread x and y metrics (fixed along the march); out-of-range entries unused
+  const double thx0 = (i <= nx) ? g.x.th[i] : 0.0, thx1 = (i + 1 <= nx) ? g.x.th[i + 1] : 0.0;
+  const double rdx0 = (i < nx) ? g.x.rd[i] : 0.0, rdxm = (i >= 1 && i - 1 < nx) ? g.x.rd[i - 1] : 0.0;
+  const double rddx0 = (i <= nx) ? g.x.rdd[i] : 0.0, rddx1 = (i + 1 <= nx) ? g.x.rdd[i + 1] : 0.0;
+  const double thy0 = (j <= ny) ? g.y.th[j] : 0.0, thy1 = (j + 1 <= ny) ? g.y.th[j + 1] : 0.0;
+  const double rdy0 = (j < ny) ? g.y.rd[j] : 0.0, rdym = (j >= 1 && j - 1 < ny) ? g.y.rd[j - 1] : 0.0;
+  const double rddy0 = (j <= ny) ? g.y.rdd[j] : 0.0, rddy1 = (j + 1 <= ny) ? g.y.rdd[j + 1] : 0.0;
+
+  load(kb - 1);
+  store(kb - 1);
+  load(kb);
+  store(kb);
+  load(kb + 1);
+  for (int k = kb; k < ke; ++k) {
+    store(k + 1);
+    __syncthreads();
+    if (k + 2 <= ke) load(k + 2);
+    const int pm = (k + 2) % 3, p0 = k % 3, pp = (k + 1) % 3;  // planes k-1, k, k+1
+    // S(arr, plane, dj, di)
+#define S(arr, pl, dj, di) sm[arr][pl][(ty + 1 + (dj)) * MPX + (tx + 1 + (di))]
+    const double thz0 = g.z.th[k], thz1 = (k + 1 <= nz) ? g.z.th[k + 1] : 0.0;
+    const double rdz0 = (k < nz) ? g.z.rd[k] : 0.0, rdzm = (k >= 1) ? g.z.rd[k - 1] : 0.0;
+    const double rddz0 = g.z.rdd[k], rddz1 = (k + 1 <= nz) ? g.z.rdd[k + 1] : 0.0;
+
+    // ---- x-momentum at the x-face (i, j, k)
+    if (k < nz && j < ny && i <= nx) {
+      double val = 0.0;
+      if (i >= 1 && i <= nx - 1) {
+        const double bc = S(3, p0, 0, 0);
+        double lap = ((S(3, p0, 0, 1) - bc) * rdx0 - (bc - S(3, p0, 0, -1)) * rdxm) * rddx0;
+        lap += ((S(3, p0, 1, 0) - bc) * rddy1 - (bc - S(3, p0, -1, 0)) * rddy0) * rdy0;
+        lap += ((S(3, pp, 0, 0) - bc) * rddz1 - (bc - S(3, pm, 0, 0)) * rddz0) * rdz0;
+        const double ac = S(0, p0, 0, 0);
+        const double am = 0.5 * (S(0, p0, 0, -1) + ac), ap = 0.5 * (ac + S(0, p0, 0, 1));
+        const double bm = 0.5 * (S(3, p0, 0, -1) + bc), bp = 0.5 * (bc + S(3, p0, 0, 1));
+        double conv = 2.0 * (ap * bp - am * bm) * rddx0;
+        // edges (xf[i], yf[j + dj])
+        double e0, e1;
+        {
+          const double av = lerp(S(1, p0, 0, -1), S(1, p0, 0, 0), thx0);
+          const double bv = lerp(S(4, p0, 0, -1), S(4, p0, 0, 0), thx0);
+          const double au = lerp(S(0, p0, -1, 0), S(0, p0, 0, 0), thy0);
+          const double bu = lerp(S(3, p0, -1, 0), S(3, p0, 0, 0), thy0);
+          e0 = av * bu + bv * au;
+        }
+        {
+          const double av = lerp(S(1, p0, 1, -1), S(1, p0, 1, 0), thx0);
+          const double bv = lerp(S(4, p0, 1, -1), S(4, p0, 1, 0), thx0);
+          const double au = lerp(S(0, p0, 0, 0), S(0, p0, 1, 0), thy1);
+          const double bu = lerp(S(3, p0, 0, 0), S(3, p0, 1, 0), thy1);
+          e1 = av * bu + bv * au;
+        }
+        conv += (e1 - e0) * rdy0;
+        // edges (xf[i], zf[k + dk])
+        {
+          const double aw = lerp(S(2, p0, 0, -1), S(2, p0, 0, 0), thx0);
+          const double bw = lerp(S(5, p0, 0, -1), S(5, p0, 0, 0), thx0);
+          const double au = lerp(S(0, pm, 0, 0), S(0, p0, 0, 0), thz0);
+          const double bu = lerp(S(3, pm, 0, 0), S(3, p0, 0, 0), thz0);
+          e0 = aw * bu + bw * au;
+        }
+        {
+          const double aw = lerp(S(2, pp, 0, -1), S(2, pp, 0, 0), thx0);
+          const double bw = lerp(S(5, pp, 0, -1), S(5, pp, 0, 0), thx0);
+          const double au = lerp(S(0, p0, 0, 0), S(0, pp, 0, 0), thz1);
+          const double bu = lerp(S(3, p0, 0, 0), S(3, pp, 0, 0), thz1);
+          e1 = aw * bu + bw * au;
+        }
+        conv += (e1 - e0) * rdz0;
+        val = rre * lap - s * conv;
+      }
+      out[((size_t)k * ny + j) * (nx + 1) + i] = val;
+    }
+
+    // ---- y-momentum at the y-face (i, j, k)
+    if (k < nz && j <= ny && i < nx) {
+      double val = 0.0;
+      if (j >= 1 && j <= ny - 1) {
+        const double bc = S(4, p0, 0, 0);
+        double lap = ((S(4, p0, 1, 0) - bc) * rdy0 - (bc - S(4, p0, -1, 0)) * rdym) * rddy0;
+        lap += ((S(4, p0, 0, 1) - bc) * rddx1 - (bc - S(4, p0, 0, -1)) * rddx0) * rdx0;
+        lap += ((S(4, pp, 0, 0) - bc) * rddz1 - (bc - S(4, pm, 0, 0)) * rddz0) * rdz0;
+        double e0, e1;
+        // edges (xf[i + di], yf[j])
+        {
+          const double au = lerp(S(0, p0, -1, 0), S(0, p0, 0, 0), thy0);
+          const double bu = lerp(S(3, p0, -1, 0), S(3, p0, 0, 0), thy0);
+          const double av = lerp(S(1, p0, 0, -1), S(1, p0, 0, 0), thx0);
+          const double bv = lerp(S(4, p0, 0, -1), S(4, p0, 0, 0), thx0);
+          e0 = au * bv + bu * av;
+        }
+        {
+          const double au = lerp(S(0, p0, -1, 1), S(0, p0, 0, 1), thy0);
+          const double bu = lerp(S(3, p0, -1, 1), S(3, p0, 0, 1), thy0);
+          const double av = lerp(S(1, p0, 0, 0), S(1, p0, 0, 1), thx1);
+          const double bv = lerp(S(4, p0, 0, 0), S(4, p0, 0, 1), thx1);
+          e1 = au * bv + bu * av;
+        }
+        double conv = (e1 - e0) * rdx0;
+        const double ac = S(1, p0, 0, 0);
+        const double am = 0.5 * (S(1, p0, -1, 0) + ac), ap = 0.5 * (ac + S(1, p0, 1, 0));
+        const double bm = 0.5 * (S(4, p0, -1, 0) + bc), bp = 0.5 * (bc + S(4, p0, 1, 0));
+        conv += 2.0 * (ap * bp - am * bm) * rddy0;
+        // edges (yf[j], zf[k + dk])
+        {
+          const double aw = lerp(S(2, p0, -1, 0), S(2, p0, 0, 0), thy0);
+          const double bw = lerp(S(5, p0, -1, 0), S(5, p0, 0, 0), thy0);
+          const double av = lerp(S(1, pm, 0, 0), S(1, p0, 0, 0), thz0);
+          const double bv = lerp(S(4, pm, 0, 0), S(4, p0, 0, 0), thz0);
+          e0 = aw * bv + bw * av;
+        }
+        {
+          const double aw = lerp(S(2, pp, -1, 0), S(2, pp, 0, 0), thy0);
+          const double bw = lerp(S(5, pp, -1, 0), S(5, pp, 0, 0), thy0);
+          const double av = lerp(S(1, p0, 0, 0), S(1, pp, 0, 0), thz1);
+          const double bv = lerp(S(4, p0, 0, 0), S(4, pp, 0, 0), thz1);
+          e1 = aw * bv + bw * av;
+        }
+        conv += (e1 - e0) * rdz0;
+        val = rre * lap - s * conv;
+      }
+      out[nu + ((size_t)k * (ny + 1) + j) * nx + i] = val;
+    }
+
+    // ---- z-momentum at the z-face (i, j, k)
+    if (k <= nz && j < ny && i < nx) {
+      double val = 0.0;
+      if (k >= 1 && k <= nz - 1) {
+        const double bc = S(5, p0, 0, 0);
+        double lap = ((S(5, pp, 0, 0) - bc) * rdz0 - (bc - S(5, pm, 0, 0)) * rdzm) * rddz0;
+        lap += ((S(5, p0, 0, 1) - bc) * rddx1 - (bc - S(5, p0, 0, -1)) * rddx0) * rdx0;
+        lap += ((S(5, p0, 1, 0) - bc) * rddy1 - (bc - S(5, p0, -1, 0)) * rddy0) * rdy0;
+        double e0, e1;
+        // edges (xf[i + di], zf[k])
+        {
+          const double au = lerp(S(0, pm, 0, 0), S(0, p0, 0, 0), thz0);
+          const double bu = lerp(S(3, pm, 0, 0), S(3, p0, 0, 0), thz0);
+          const double aw = lerp(S(2, p0, 0, -1), S(2, p0, 0, 0), thx0);
+          const double bw = lerp(S(5, p0, 0, -1), S(5, p0, 0, 0), thx0);
+          e0 = au * bw + bu * aw;
+        }
+        {
+          const double au = lerp(S(0, pm, 0, 1), S(0, p0, 0, 1), thz0);
+          const double bu = lerp(S(3, pm, 0, 1), S(3, p0, 0, 1), thz0);
+          const double aw = lerp(S(2, p0, 0, 0), S(2, p0, 0, 1), thx1);
+          const double bw = lerp(S(5, p0, 0, 0), S(5, p0, 0, 1), thx1);
+          e1 = au * bw + bu * aw;
+        }
+        double conv = (e1 - e0) * rdx0;
+        // edges (yf[j + dj], zf[k])
+        {
+          const double av = lerp(S(1, pm, 0, 0), S(1, p0, 0, 0), thz0);
+          const double bv = lerp(S(4, pm, 0, 0), S(4, p0, 0, 0), thz0);
+          const double aw = lerp(S(2, p0, -1, 0), S(2, p0, 0, 0), thy0);
+          const double bw = lerp(S(5, p0, -1, 0), S(5, p0, 0, 0), thy0);
+          e0 = av * bw + bv * aw;
+        }
+        {
+          const double av = lerp(S(1, pm, 1, 0), S(1, p0, 1, 0), thz0);
+          const double bv = lerp(S(4, pm, 1, 0), S(4, p0, 1, 0), thz0);
+          const double aw = lerp(S(2, p0, 0, 0), S(2, p0, 1, 0), thy1);
+          const double bw = lerp(S(5, p0, 0, 0), S(5, p0, 1, 0), thy1);
+          e1 = av * bw + bv * aw;
+        }
+        conv += (e1 - e0) * rdy0;
+        const double ac = S(2, p0, 0, 0);
+        const double am = 0.5 * (S(2, pm, 0, 0) + ac), ap = 0.5 * (ac + S(2, pp, 0, 0));
+        const double bm = 0.5 * (S(5, pm, 0, 0) + bc), bp = 0.5 * (bc + S(5, pp, 0, 0));
+        conv += 2.0 * (ap * bp - am * bm) * rddz0;
+        val = rre * lap - s * conv;
+      }
+      out[nu + nv + ((size_t)k * ny + j) * nx + i] = val;
+    }
+#undef S
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- divergence
+__global__ void __launch_bounds__(kReduceBlock) k_divergence(GridDev g, Vel V, double* __restrict__ r,
+                                                             double* __restrict__ partials) {
+  const int nx = g.x.n, ny = g.y.n, nz = g.z.n;
+  const size_t ncell = (size_t)nx * ny * nz;
+  const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double contrib = 0.0;
+  if (c < ncell) {
+    const int i = (int)(c % nx);
+    const int j = (int)((c / nx) % ny);
+    const int k = (int)(c / ((size_t)nx * ny));
+    const double dv = (V.U(k, j, i + 1) - V.U(k, j, i)) * g.x.rd[i] +
+                      (V.V(k, j + 1, i) - V.V(k, j, i)) * g.y.rd[j] +
+                      (V.W(k + 1, j, i) - V.W(k, j, i)) * g.z.rd[k];
+    if (r) r[c] = dv;
+    contrib = g.x.d[i] * g.y.d[j] * g.z.d[k] * dv * dv;
+  }
+  if (partials) {
+    const double t = block_sum(contrib);
+    if (threadIdx.x == 0) partials[blockIdx.x] = t;
+  }
+}
+
+// ---------------------------------------------------------------- correction
+__global__ void __launch_bounds__(256) k_correct(GridDev g, const double* __restrict__ w,
+                                                 const double* __restrict__ phi, double* __restrict__ v,
+                                                 double* __restrict__ p, int accumulate) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  const int k = blockIdx.z;
+  const int nx = g.x.n, ny = g.y.n, nz = g.z.n;
+  if (i > nx || j > ny || k > nz) return;
+  const Idx I{nx, ny, nz};
+  const size_t nu = (size_t)(nx + 1) * ny * nz, nv = (size_t)nx * (ny + 1) * nz;
+  const double* src = accumulate ? v : w;
+  // branch-free loads: in-range clamped cell indices, wall faces selected to 0
+  const int ic = min(i, nx - 1), jc = min(j, ny - 1), kc = min(k, nz - 1);
+  const double pc = phi[I.c(kc, jc, ic)];
+  if (j < ny && k < nz) {
+    const size_t q = I.u(k, j, i);
+    const bool in = (i > 0) & (i < nx);
+    const double pw = phi[I.c(k, j, max(i - 1, 0))], pe = phi[I.c(k, j, ic)], s = src[q];
+    const double val = s - (pe - pw) * g.x.rdd[i];
+    v[q] = in ? val : 0.0;
+  }
+  if (i < nx && k < nz) {
+    const size_t q = nu + I.v(k, j, i);
+    const bool in = (j > 0) & (j < ny);
+    const double ps = phi[I.c(k, max(j - 1, 0), i)], pn = phi[I.c(k, jc, i)], s = src[q];
+    const double val = s - (pn - ps) * g.y.rdd[j];
+    v[q] = in ? val : 0.0;
+  }
+  if (i < nx && j < ny) {
+    const size_t q = nu + nv + I.w(k, j, i);
+    const bool in = (k > 0) & (k < nz);
+    const double pb = phi[I.c(max(k - 1, 0), j, i)], s = src[q];
+    const double val = s - (pc - pb) * g.z.rdd[k];
+    v[q] = in ? val : 0.0;
+    if (p && k < nz) {
+      const size_t c = I.c(k, j, i);
+      p[c] = accumulate ? p[c] + pc : pc;
+    }
+  }
+}
+
+}  // namespace
+
+// ==================================================================== launchers
+hipError_t launch_momentum(const GridDev& g, const double* a, const double* b, double* out, double rre, double s,
+                           bool lid, double lid_u, double lid_v, hipStream_t st) {
+  const int nx = g.x.n, ny = g.y.n, nz = g.z.n;
+  const int kchunk = 24;
+  dim3 block(MTX, MTY, 1);
+  dim3 grid(blocks_for(nx + 1, MTX), blocks_for(ny + 1, MTY), blocks_for(nz + 1, kchunk));
+  if (lid)
+    hipLaunchKernelGGL(k_momentum<true>, grid, block, 0, st, g, a, b, out, rre, s, lid_u, lid_v, kchunk);
+  else
+    hipLaunchKernelGGL(k_momentum<false>, grid, block, 0, st, g, a, b, out, rre, s, 0.0, 0.0, kchunk);
+  return hipGetLastError();
+}
+
+hipError_t launch_divergence(const GridDev& g, const double* v, double* r, double* partials, int* nparts,
+                             hipStream_t st) {
+  const int nx = g.x.n, ny = g.y.n, nz = g.z.n;
+  const VelLayout L = vel_layout(nx, ny, nz);
+  Vel V{v, v + L.ov(), v + L.ow(), Idx{nx, ny, nz}};
+  const size_t ncell = (size_t)nx * ny * nz;
+  const unsigned nb = blocks_for(ncell, kReduceBlock);
+  if (nparts) *nparts = (int)nb;
+  hipLaunchKernelGGL(k_divergence, dim3(nb), dim3(kReduceBlock), 0, st, g, V, r, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_correct(const GridDev& g, const double* w, const double* phi, double* v, double* p,
+                          bool accumulate, hipStream_t st) {
+  const int nx = g.x.n, ny = g.y.n, nz = g.z.n;
+  dim3 block(64, 4, 1);
+  dim3 grid(blocks_for(nx + 1, 64), blocks_for(ny + 1, 4), nz + 1);
+  hipLaunchKernelGGL(k_correct, grid, block, 0, st, g, w, phi, v, p, accumulate ? 1 : 0);
+  return hipGetLastError();
+}
+
+}  // namespace lk

@@ -153,6 +153,59 @@ int lc_krylov_vector(lc_ctx* ctx, const double* v_in, double* v_out, double* p_o
  * S[n*n] row-major with the modes as columns (S^T M S = I), Wf[n*n] = S^T M. */
 int lc_axis_modes(int n, const double* faces, double* lam, double* S, double* Wf);
 
+/* Host-only utility (no GPU needed): eigenvalues of a real m x m upper
+ * Hessenberg matrix H (host, row-major; entries below the subdiagonal are
+ * ignored), the eigensolve of the Arnoldi restarts.  re, im: m doubles each
+ * (host), unordered.  LC_EINVAL if m < 1 or the QR iteration fails. */
+int lc_hessenberg_eigvals(int m, const double* H, double* re, double* im);
+
+/* -------------------------------------------------------- Krylov drivers */
+
+/* Projected steady residual F = P R(U) of the context's base flow (Section 3,
+ * Newton step 2): the residual of eqs. 1-4 with its pressure part removed by
+ * the projection.  F: velocity (device); res_inf (host) = max |F|. */
+int lc_newton_residual(lc_ctx* ctx, double* F, double* res_inf);
+
+/* One Newton step of Section 3 on the context's base flow U: F = P R(U), solve
+ * the Jacobian system (P L_U) d = F on the divergence-free space with restarted
+ * GMRES(gmres_m) on SIMPLE-evaluated Krylov vectors (modified Gram-Schmidt,
+ * float64); a restart that lowers the residual by less than 10% counts as
+ * saturation and hands its iterate to BiCGstab(2) (gmres_m = 0: BiCGstab(2)
+ * alone, as Section 3 used it at 100^3); then U <- U - d (step 4).  A saturated
+ * restart whose residual is already within sqrt(lin_tol) |F| (the rounding
+ * floor of late Newton steps) is accepted as converged.
+ * The linear solve stops at |res| <= lin_tol |F| or after max_vectors Krylov
+ * vectors (then LC_ENOTCONV, U still updated).  precision / proj_tol: form and
+ * divergence tolerance of each Krylov vector (max 8 SIMPLE passes).  Outputs
+ * (host, each may be NULL): res_inf = max |F| before the step, corr_inf =
+ * max |d|, n_vectors = Krylov vectors used, used_bicgstab = 1 if the hand-off
+ * happened.  Workspace: max(gmres_m + 1, 8) + 3 velocity vectors (library-owned). */
+int lc_newton_step(lc_ctx* ctx, double lin_tol, int gmres_m, long max_vectors, int precision, double proj_tol,
+                   double* res_inf, double* corr_inf, long* n_vectors, int* used_bicgstab);
+
+/* Leading eigenvalues of the stability problem (eq. 7): the k eigenvalues of
+ * P L_U with largest real part, by implicitly restarted Arnoldi on
+ * SIMPLE-evaluated Krylov vectors started from a seeded (SplitMix64, `seed`)
+ * random vector projected onto the divergence-free space.  Each extension
+ * orthogonalizes by modified Gram-Schmidt in float64 (repeated once when the
+ * norm drops below 1/sqrt 2 of its value); the m x m Hessenberg eigenproblem
+ * is solved in float64 on the host and the m - k unwanted Ritz values serve as
+ * exact shifts (complex pairs as real double shifts).  Ritz values of modulus
+ * below 1e-5 of the largest are treated as unwanted (they come from the gradient
+ * directions, where P L_U is zero; so are true eigenvalues that small).  Converged when every
+ * wanted pair has |h_{m+1,m} e_m^T y| <= tol |theta|.  If the k-th and (k+1)-th
+ * values are a conjugate pair both are returned.
+ * Requirements: 1 <= k <= 46, k + 3 <= m <= 100.  Outputs (host): eig_re,
+ * eig_im, resid (may be NULL): arrays of k+1 doubles, real part descending;
+ * n_out = number returned.  vec_re, vec_im (device, may be NULL): k+1
+ * velocity vectors each, the unit-norm Ritz vectors.  n_vectors (may be NULL):
+ * Krylov vectors evaluated.  Returns LC_ENOTCONV after max_restarts restarts
+ * without convergence (outputs hold the last Ritz values).  Workspace:
+ * 2 (m + 1) velocity vectors (library-owned). */
+int lc_arnoldi_leading(lc_ctx* ctx, int k, int m, double tol, int max_restarts, unsigned long long seed,
+                       int precision, double proj_tol, double* eig_re, double* eig_im, double* resid,
+                       double* vec_re, double* vec_im, int* n_out, long* n_vectors);
+
 /* ---------------------------------------------------------- vector helpers */
 
 /* Euclidean dot product of two velocity vectors (host result). */

@@ -156,6 +156,55 @@ class Context:
                          allow_notconv=True)
         return v, p, dict(st.as_dict(), converged=(rc == 0))
 
+    # ------------------------------------------------------ Krylov drivers
+    def newton_residual(self, out=None):
+        """(F = P R(U), max |F|) for the context's base flow."""
+        out = self.vel() if out is None else out
+        r = C.c_double()
+        self._check(self.lib.lc_newton_residual(self._h, self._ptr(out, self.nvel, "F"), C.byref(r)))
+        return out, r.value
+
+    def newton_step(self, lin_tol=1e-10, gmres_m=100, max_vectors=5000, precision=FP64, proj_tol=1e-12):
+        """One Newton step on the context's base flow (updated in place)."""
+        ri, ci, nv, bi = C.c_double(), C.c_double(), C.c_long(), C.c_int()
+        rc = self._check(self.lib.lc_newton_step(self._h, float(lin_tol), int(gmres_m), int(max_vectors),
+                                                 int(precision), float(proj_tol), C.byref(ri), C.byref(ci),
+                                                 C.byref(nv), C.byref(bi)), allow_notconv=True)
+        return {"res_inf": ri.value, "corr_inf": ci.value, "n_vectors": nv.value, "bicgstab": bool(bi.value),
+                "converged": rc == 0}
+
+    def newton(self, tol=1e-10, max_steps=12, **kw):
+        """Newton iterations from the current base flow until max |P R(U)| <= tol."""
+        hist = []
+        for _ in range(max_steps):
+            _, r = self.newton_residual()
+            hist.append(r)
+            if r <= tol:
+                break
+            self.newton_step(**kw)
+        return hist
+
+    def arnoldi_leading(self, k=4, m=20, tol=1e-10, max_restarts=200, seed=1, precision=FP64, proj_tol=1e-12,
+                        vectors=False):
+        """Leading eigenvalues (largest real part) of eq. 7 by implicitly restarted Arnoldi."""
+        torch = _torch()
+        re = np.zeros(k + 1); im = np.zeros(k + 1); res = np.zeros(k + 1)
+        vre = vim = None
+        if vectors:
+            vre = torch.zeros((k + 1, self.nvel), dtype=torch.float64, device=self.device)
+            vim = torch.zeros((k + 1, self.nvel), dtype=torch.float64, device=self.device)
+        nout, nvec = C.c_int(), C.c_long()
+        p = lambda a: a.ctypes.data_as(C.c_void_p)
+        rc = self._check(self.lib.lc_arnoldi_leading(
+            self._h, int(k), int(m), float(tol), int(max_restarts), C.c_ulonglong(seed), int(precision),
+            float(proj_tol), p(re), p(im), p(res), C.c_void_p(vre.data_ptr()) if vectors else None,
+            C.c_void_p(vim.data_ptr()) if vectors else None, C.byref(nout), C.byref(nvec)), allow_notconv=True)
+        n = nout.value
+        out = {"eig": re[:n] + 1j * im[:n], "resid": res[:n], "n_vectors": nvec.value, "converged": rc == 0}
+        if vectors:
+            out["vectors"] = (vre[:n], vim[:n])
+        return out
+
     # ----------------------------------------------------------- profiling
     def profile(self, on=True):
         self._check(self.lib.lc_profile_enable(self._h, 1 if on else 0))

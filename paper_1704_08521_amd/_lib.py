@@ -59,6 +59,12 @@ _SIGS = {
     "lc_krylov_vector": (_I, [_P, _P, _P, _P, _I, _D, _I, C.POINTER(Stats)]),
     "lc_dot": (_I, [_P, _P, _P, C.POINTER(_D)]),
     "lc_axis_modes": (_I, [_I, _P, _P, _P, _P]),
+    "lc_hessenberg_eigvals": (_I, [_I, _P, _P, _P]),
+    "lc_newton_residual": (_I, [_P, _P, C.POINTER(_D)]),
+    "lc_newton_step": (_I, [_P, _D, _I, C.c_long, _I, _D, C.POINTER(_D), C.POINTER(_D), C.POINTER(C.c_long),
+                            C.POINTER(_I)]),
+    "lc_arnoldi_leading": (_I, [_P, _I, _I, _D, _I, C.c_ulonglong, _I, _D, _P, _P, _P, _P, _P, C.POINTER(_I),
+                                C.POINTER(C.c_long)]),
     "lc_profile_enable": (_I, [_P, _I]),
     "lc_profile_read": (_I, [_P, _I, C.POINTER(_D), C.POINTER(C.c_long)]),
     "lc_profile_name": (C.c_char_p, [_I]),

@@ -9,89 +9,17 @@
 #include <string>
 #include <vector>
 
-#include "../../include/lidkrylov.h"
+#include "lk_ctx.h"
 #include "lk_internal.h"
 #include "lk_linalg.h"
 
 using namespace lk;
 
 namespace {
-
 std::string g_create_error;
-
-template <typename T>
-struct DevBuf {
-  T* p = nullptr;
-  size_t n = 0;
-};
-
-struct AxisHost {
-  std::vector<double> xf, d, dd, th, rd, rdd;
-  void build(const double* faces, int n) {
-    xf.assign(faces, faces + n + 1);
-    d.resize(n);
-    for (int i = 0; i < n; ++i) d[i] = xf[i + 1] - xf[i];
-    std::vector<double> c(n);
-    for (int i = 0; i < n; ++i) c[i] = 0.5 * (xf[i] + xf[i + 1]);
-    dd.resize(n + 1);
-    dd[0] = 0.5 * d[0];
-    dd[n] = 0.5 * d[n - 1];
-    for (int i = 1; i < n; ++i) dd[i] = c[i] - c[i - 1];
-    th.assign(n + 1, 0.5);
-    for (int i = 1; i < n; ++i) th[i] = d[i - 1] / (2.0 * dd[i]);
-    rd.resize(n);
-    rdd.resize(n + 1);
-    for (int i = 0; i < n; ++i) rd[i] = 1.0 / d[i];
-    for (int i = 0; i <= n; ++i) rdd[i] = 1.0 / dd[i];
-  }
-};
-
-// Tensor-product factorization of one axis, device copies in float64 and float32.
-struct AxisModes {
-  double* lam = nullptr;          // n eigenvalues
-  double *F = nullptr, *Bk = nullptr, *FT = nullptr, *BkT = nullptr;
-  float *F32 = nullptr, *Bk32 = nullptr, *FT32 = nullptr, *BkT32 = nullptr;
-};
-
 }  // namespace
 
-struct lc_ctx {
-  int nx = 0, ny = 0, nz = 0;
-  hipStream_t stream = nullptr;
-  std::string err;
-  double re = 1.0, alpha = 0.0;
-  bool grid_ready = false;
-  AxisHost ax[3];  // x, y, z
-  double* metric = nullptr;  // device storage of rd, rdd, th, d for the three axes
-  GridDev g{};
-  AxisModes modes[3];
-  void* modes_mem = nullptr;
-  int zero_mode[3] = {0, 0, 0};
-  // fields
-  double* U = nullptr;   // base flow (velocity)
-  double* w = nullptr;   // momentum work vector (velocity)
-  double* r = nullptr;   // divergence (cell)
-  double* phi = nullptr; // correction (cell)
-  double* t1 = nullptr;  // transform temporaries (cell)
-  double* t2 = nullptr;
-  float *r32 = nullptr, *t1_32 = nullptr, *t2_32 = nullptr;
-  double* partials = nullptr;
-  int max_parts = 0;
-  double* dsum = nullptr;   // device scalar
-  double* hsum = nullptr;   // pinned host scalar
-  size_t nvel = 0, ncell = 0;
-  // profiling: event pairs around launches on `stream`
-  struct Rec {
-    int kid;
-    hipEvent_t a, b;
-  };
-  bool prof = false;
-  std::vector<Rec> recs;
-  std::vector<hipEvent_t> ev_pool;
-  size_t ev_used = 0;
-};
-
-namespace {
+namespace lk {
 
 int fail(lc_ctx* c, int code, const char* fmt, ...) {
   char buf[512];
@@ -104,11 +32,7 @@ int fail(lc_ctx* c, int code, const char* fmt, ...) {
   return code;
 }
 
-#define HIPCHK(c, expr)                                                                       \
-  do {                                                                                        \
-    hipError_t e_ = (expr);                                                                   \
-    if (e_ != hipSuccess) return fail((c), LC_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
-  } while (0)
+
 
 hipEvent_t take_event(lc_ctx* c) {
   if (c->ev_used < c->ev_pool.size()) return c->ev_pool[c->ev_used++];
@@ -119,20 +43,7 @@ hipEvent_t take_event(lc_ctx* c) {
   return e;
 }
 
-// Launch with optional event timing (kernel class `kid`).
-#define KLAUNCH(c, kid, expr)                                                  \
-  do {                                                                         \
-    hipEvent_t a_ = nullptr;                                                   \
-    if ((c)->prof && (a_ = take_event(c))) (void)hipEventRecord(a_, (c)->stream); \
-    HIPCHK(c, expr);                                                           \
-    if ((c)->prof && a_) {                                                     \
-      hipEvent_t b_ = take_event(c);                                           \
-      if (b_) {                                                                \
-        (void)hipEventRecord(b_, (c)->stream);                                 \
-        (c)->recs.push_back({(kid), a_, b_});                                  \
-      }                                                                        \
-    }                                                                          \
-  } while (0)
+
 
 template <typename T>
 hipError_t dalloc(T** p, size_t n) {
@@ -293,7 +204,27 @@ int check_ready(lc_ctx* c) {
 
 bool aligned(const void* p) { return p && ((uintptr_t)p % 8 == 0); }
 
-}  // namespace
+int reduce_max_to_host(lc_ctx* c, int nparts, double* out) {
+  KLAUNCH(c, LC_K_REDUCE, launch_max(c->partials, nparts, c->dsum, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->hsum, c->dsum, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  *out = *c->hsum;
+  return LC_OK;
+}
+
+int vdot(lc_ctx* c, const double* a, const double* b, double* out) {
+  int np = 0;
+  KLAUNCH(c, LC_K_VECTOR, launch_dot_partials(a, b, c->nvel, c->partials, &np, c->stream));
+  return reduce_to_host(c, np, out);
+}
+
+int vmaxabs(lc_ctx* c, const double* a, double* out) {
+  int np = 0;
+  KLAUNCH(c, LC_K_VECTOR, launch_maxabs_partials(a, c->nvel, c->partials, &np, c->stream));
+  return reduce_max_to_host(c, np, out);
+}
+
+}  // namespace lk
 
 extern "C" {
 
@@ -322,7 +253,9 @@ int lc_create(lc_ctx** out, int nx, int ny, int nz, void* hip_stream) {
             dalloc(&c->t1, c->ncell) == hipSuccess && dalloc(&c->t2, c->ncell) == hipSuccess &&
             dalloc(&c->r32, c->ncell) == hipSuccess && dalloc(&c->t1_32, c->ncell) == hipSuccess &&
             dalloc(&c->t2_32, c->ncell) == hipSuccess && dalloc(&c->partials, c->max_parts) == hipSuccess &&
-            dalloc(&c->dsum, 1) == hipSuccess &&
+            dalloc(&c->dsum, 1) == hipSuccess && dalloc(&c->dsmall, kSmall) == hipSuccess &&
+            dalloc(&c->pk, c->ncell) == hipSuccess &&
+            hipHostMalloc((void**)&c->hsmall, kSmall * sizeof(double), hipHostMallocDefault) == hipSuccess &&
             hipHostMalloc((void**)&c->hsum, sizeof(double), hipHostMallocDefault) == hipSuccess;
   if (!ok) {
     lc_destroy(c);
@@ -347,10 +280,11 @@ int lc_destroy(lc_ctx* c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   else (void)hipDeviceSynchronize();
   void* ptrs[] = {c->U, c->w, c->r, c->phi, c->t1, c->t2, c->r32, c->t1_32, c->t2_32, c->partials,
-                  c->dsum, c->metric, c->modes_mem};
+                  c->dsum, c->metric, c->modes_mem, c->dsmall, c->pk, c->kws};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (c->hsum) (void)hipHostFree(c->hsum);
+  if (c->hsmall) (void)hipHostFree(c->hsmall);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   delete c;
   return LC_OK;

@@ -1,0 +1,132 @@
+// Context of the C ABI and the helpers shared by the host-side drivers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/lidkrylov.h"
+#include "lk_internal.h"
+
+namespace lk {
+
+struct AxisHost {
+  std::vector<double> xf, d, dd, th, rd, rdd;
+  void build(const double* faces, int n) {
+    xf.assign(faces, faces + n + 1);
+    d.resize(n);
+    for (int i = 0; i < n; ++i) d[i] = xf[i + 1] - xf[i];
+    std::vector<double> c(n);
+    for (int i = 0; i < n; ++i) c[i] = 0.5 * (xf[i] + xf[i + 1]);
+    dd.resize(n + 1);
+    dd[0] = 0.5 * d[0];
+    dd[n] = 0.5 * d[n - 1];
+    for (int i = 1; i < n; ++i) dd[i] = c[i] - c[i - 1];
+    th.assign(n + 1, 0.5);
+    for (int i = 1; i < n; ++i) th[i] = d[i - 1] / (2.0 * dd[i]);
+    rd.resize(n);
+    rdd.resize(n + 1);
+    for (int i = 0; i < n; ++i) rd[i] = 1.0 / d[i];
+    for (int i = 0; i <= n; ++i) rdd[i] = 1.0 / dd[i];
+  }
+};
+
+// Tensor-product factorization of one axis, device copies in float64 and float32.
+struct AxisModes {
+  double* lam = nullptr;          // n eigenvalues
+  double *F = nullptr, *Bk = nullptr, *FT = nullptr, *BkT = nullptr;
+  float *F32 = nullptr, *Bk32 = nullptr, *FT32 = nullptr, *BkT32 = nullptr;
+};
+
+}  // namespace lk
+
+struct lc_ctx {
+  using AxisHost = lk::AxisHost;
+  using AxisModes = lk::AxisModes;
+  using GridDev = lk::GridDev;
+  int nx = 0, ny = 0, nz = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  double re = 1.0, alpha = 0.0;
+  bool grid_ready = false;
+  AxisHost ax[3];  // x, y, z
+  double* metric = nullptr;  // device storage of rd, rdd, th, d for the three axes
+  GridDev g{};
+  AxisModes modes[3];
+  void* modes_mem = nullptr;
+  int zero_mode[3] = {0, 0, 0};
+  // fields
+  double* U = nullptr;   // base flow (velocity)
+  double* w = nullptr;   // momentum work vector (velocity)
+  double* r = nullptr;   // divergence (cell)
+  double* phi = nullptr; // correction (cell)
+  double* t1 = nullptr;  // transform temporaries (cell)
+  double* t2 = nullptr;
+  float *r32 = nullptr, *t1_32 = nullptr, *t2_32 = nullptr;
+  double* partials = nullptr;
+  int max_parts = 0;
+  double* dsum = nullptr;   // device scalar
+  double* hsum = nullptr;   // pinned host scalar
+  size_t nvel = 0, ncell = 0;
+  // profiling: event pairs around launches on `stream`
+  struct Rec {
+    int kid;
+    hipEvent_t a, b;
+  };
+  // Krylov drivers: basis workspace (grown on demand), small device/host scalars,
+  // the discarded pressure of Krylov maps
+  double* kws = nullptr;
+  size_t kws_n = 0;
+  double* dsmall = nullptr;  // kSmall doubles
+  double* hsmall = nullptr;  // kSmall doubles, pinned
+  double* pk = nullptr;      // cell
+  bool prof = false;
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+};
+
+
+namespace lk {
+
+constexpr int kSmall = 16384;
+
+int fail(lc_ctx* c, int code, const char* fmt, ...);
+hipEvent_t take_event(lc_ctx* c);
+double now_ms();
+bool aligned(const void* p);
+int check_ready(lc_ctx* c);
+// fixed-order device reduction of c->partials (sum or max) to a host scalar
+int reduce_to_host(lc_ctx* c, int nparts, double* out);
+int reduce_max_to_host(lc_ctx* c, int nparts, double* out);
+// |D v|_V (r receives D v when not null)
+int vnorm_div(lc_ctx* c, const double* v, double* r, double* out);
+// pressure-correction solve in the given precision
+int poisson(lc_ctx* c, const double* r, double* phi, int precision);
+// Euclidean dot product / max |x| of velocity vectors, host results
+int vdot(lc_ctx* c, const double* a, const double* b, double* out);
+int vmaxabs(lc_ctx* c, const double* a, double* out);
+
+}  // namespace lk
+
+#define HIPCHK(c, expr)                                                                           \
+  do {                                                                                            \
+    hipError_t e_ = (expr);                                                                       \
+    if (e_ != hipSuccess) return lk::fail((c), LC_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+// Launch with optional event timing (kernel class `kid`).
+#define KLAUNCH(c, kid, expr)                                                        \
+  do {                                                                               \
+    hipEvent_t a_ = nullptr;                                                         \
+    if ((c)->prof && (a_ = lk::take_event(c))) (void)hipEventRecord(a_, (c)->stream); \
+    HIPCHK(c, expr);                                                                 \
+    if ((c)->prof && a_) {                                                           \
+      hipEvent_t b_ = lk::take_event(c);                                             \
+      if (b_) {                                                                      \
+        (void)hipEventRecord(b_, (c)->stream);                                       \
+        (c)->recs.push_back({(kid), a_, b_});                                        \
+      }                                                                              \
+    }                                                                                \
+  } while (0)

@@ -67,6 +67,23 @@ hipError_t launch_sum(const double* partials, int n, double* out, hipStream_t st
 hipError_t launch_dot_partials(const double* a, const double* b, size_t n, double* partials,
                                int* nparts, hipStream_t st);
 
+// Fixed-order max of n partials into out[0]; per-block partial max |a|.
+hipError_t launch_max(const double* partials, int n, double* out, hipStream_t st);
+hipError_t launch_maxabs_partials(const double* a, size_t n, double* partials, int* nparts, hipStream_t st);
+
+// Modified Gram-Schmidt step: w -= sign*h[0] * vi (h in device memory); if next is
+// set, per-block partials of next . w_new.
+hipError_t launch_mgs(double* w, const double* vi, const double* next, const double* h, double sign, size_t n,
+                      double* partials, int* nparts, hipStream_t st);
+
+// y += sign * a_dev[0] / d_dev[0] * x (d_dev may be null): scalars from device memory.
+hipError_t launch_axpy_dev(size_t n, const double* a_dev, const double* d_dev, double sign, const double* x,
+                           double* y, hipStream_t st);
+
+// out[c] = sum_i V[i] Q[i][c] for c < nc (<= 48), i < nv; vectors ld / ldo apart.
+hipError_t launch_combine(const double* V, long ld, int nv, const double* Q, int nc, double* out, long ldo, size_t n,
+                          hipStream_t st);
+
 // y = a*x + y ; x *= a ; y = x
 hipError_t launch_axpy(size_t n, double a, const double* x, double* y, hipStream_t st);
 hipError_t launch_scale(size_t n, double a, double* x, hipStream_t st);

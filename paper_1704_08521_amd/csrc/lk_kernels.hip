@@ -83,7 +83,130 @@ __global__ void k_zero_walls(double* __restrict__ vel, int nx, int ny, int nz) {
   }
 }
 
+__global__ void __launch_bounds__(1024) k_max(const double* __restrict__ partials, int n, double* __restrict__ out) {
+  __shared__ double sh[1024];
+  double t = 0.0;
+  for (int q = threadIdx.x; q < n; q += 1024) t = fmax(t, partials[q]);
+  sh[threadIdx.x] = t;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+__device__ __forceinline__ double block_max(double x) {
+  __shared__ double red[kReduceBlock / 64];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x = fmax(x, __shfl_down(x, off, 64));
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) red[wid] = x;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int q = 0; q < kReduceBlock / 64; ++q) t = fmax(t, red[q]);
+  return t;
+}
+
+__global__ void __launch_bounds__(kReduceBlock) k_maxabs(const double* __restrict__ a, size_t n,
+                                                         double* __restrict__ partials) {
+  double t = 0.0;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) t = fmax(t, fabs(a[q]));
+  t = block_max(t);
+  if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+// One modified Gram-Schmidt update with the coefficient read from device memory:
+// w -= h * v_i, and (if next) partial sums of next . w_new for the following step.
+__global__ void __launch_bounds__(kReduceBlock) k_mgs(double* __restrict__ w, const double* __restrict__ vi,
+                                                      const double* __restrict__ next, const double* __restrict__ h,
+                                                      double sign, size_t n, double* __restrict__ partials) {
+  const double c = sign * h[0];
+  double t = 0.0;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) {
+    const double x = w[q] - c * vi[q];
+    w[q] = x;
+    if (next) t += next[q] * x;
+  }
+  if (next) {
+    t = block_sum(t);
+    if (threadIdx.x == 0) partials[blockIdx.x] = t;
+  }
+}
+
+// y = a * x + y with a = sign * (*a_dev) / (*d_dev) read from device memory (d_dev may be null).
+__global__ void k_axpy_dev(size_t n, const double* __restrict__ a_dev, const double* __restrict__ d_dev,
+                           double sign, const double* __restrict__ x, double* __restrict__ y) {
+  const double a = sign * a_dev[0] / (d_dev ? d_dev[0] : 1.0);
+  const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < n) y[q] += a * x[q];
+}
+
+// out[c] = sum_i V[i] * Q[i][c] (c < nc, i < nv), basis vectors ld apart; Q row-major nv x nc.
+template <int NC>
+__global__ void __launch_bounds__(256) k_combine(const double* __restrict__ V, long ld, int nv,
+                                                 const double* __restrict__ Q, int nc, double* __restrict__ out,
+                                                 long ldo, size_t n) {
+  const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  double acc[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+  for (int i = 0; i < nv; ++i) {
+    const double v = V[(size_t)i * ld + q];
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+      if (c < nc) acc[c] += v * Q[i * nc + c];
+  }
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+    if (c < nc) out[(size_t)c * ldo + q] = acc[c];
+}
+
 }  // namespace
+
+hipError_t launch_max(const double* partials, int n, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_max, dim3(1), dim3(1024), 0, st, partials, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_maxabs_partials(const double* a, size_t n, double* partials, int* nparts, hipStream_t st) {
+  unsigned nb = blocks_for(n, kReduceBlock);
+  if (nb > 4096) nb = 4096;
+  if (nparts) *nparts = (int)nb;
+  hipLaunchKernelGGL(k_maxabs, dim3(nb), dim3(kReduceBlock), 0, st, a, n, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_mgs(double* w, const double* vi, const double* next, const double* h, double sign, size_t n,
+                      double* partials, int* nparts, hipStream_t st) {
+  unsigned nb = blocks_for(n, kReduceBlock);
+  if (nb > 4096) nb = 4096;
+  if (nparts) *nparts = (int)nb;
+  hipLaunchKernelGGL(k_mgs, dim3(nb), dim3(kReduceBlock), 0, st, w, vi, next, h, sign, n, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy_dev(size_t n, const double* a_dev, const double* d_dev, double sign, const double* x,
+                           double* y, hipStream_t st) {
+  hipLaunchKernelGGL(k_axpy_dev, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, a_dev, d_dev, sign, x, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_combine(const double* V, long ld, int nv, const double* Q, int nc, double* out, long ldo, size_t n,
+                          hipStream_t st) {
+  dim3 grid(blocks_for(n, 256)), block(256);
+  if (nc <= 1) hipLaunchKernelGGL(k_combine<1>, grid, block, 0, st, V, ld, nv, Q, nc, out, ldo, n);
+  else if (nc <= 2) hipLaunchKernelGGL(k_combine<2>, grid, block, 0, st, V, ld, nv, Q, nc, out, ldo, n);
+  else if (nc <= 8) hipLaunchKernelGGL(k_combine<8>, grid, block, 0, st, V, ld, nv, Q, nc, out, ldo, n);
+  else if (nc <= 24) hipLaunchKernelGGL(k_combine<24>, grid, block, 0, st, V, ld, nv, Q, nc, out, ldo, n);
+  else if (nc <= 48) hipLaunchKernelGGL(k_combine<48>, grid, block, 0, st, V, ld, nv, Q, nc, out, ldo, n);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
 
 hipError_t launch_sum(const double* partials, int n, double* out, hipStream_t st) {
   hipLaunchKernelGGL(k_sum, dim3(1), dim3(1024), 0, st, partials, n, out);

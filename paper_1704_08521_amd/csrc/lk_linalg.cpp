@@ -74,6 +74,185 @@ bool sym_tridiag_eig(int n, std::vector<double> a, std::vector<double> b, std::v
   return true;
 }
 
+bool hess_eigvals(int m, const std::vector<double>& H, std::vector<cplx>& lam) {
+  std::vector<cplx> A(H.begin(), H.begin() + (size_t)m * m);
+  auto at = [&](int r, int c) -> cplx& { return A[(size_t)r * m + c]; };
+  const double eps = 2.220446049250313e-16;
+  double hnorm = 0.0;
+  for (double x : H) hnorm = std::max(hnorm, std::fabs(x));
+  lam.clear();
+  int hi = m - 1, iter = 0, total = 0;
+  while (hi >= 0) {
+    if (hi == 0) {
+      lam.push_back(at(0, 0));
+      break;
+    }
+    int l = hi;
+    while (l > 0) {
+      double s = std::abs(at(l, l)) + std::abs(at(l - 1, l - 1));
+      if (s == 0.0) s = hnorm;
+      if (std::abs(at(l, l - 1)) <= eps * s) {
+        at(l, l - 1) = 0.0;
+        break;
+      }
+      --l;
+    }
+    if (l == hi) {
+      lam.push_back(at(hi, hi));
+      --hi;
+      iter = 0;
+      continue;
+    }
+    if (++iter > 60 || ++total > 60 * m) return false;
+    // Wilkinson shift: eigenvalue of the trailing 2x2 block nearer to its last entry
+    const cplx a = at(hi - 1, hi - 1), b = at(hi - 1, hi), c = at(hi, hi - 1), d = at(hi, hi);
+    const cplx half_tr = 0.5 * (a + d);
+    const cplx disc = std::sqrt(half_tr * half_tr - (a * d - b * c));
+    const cplx mu1 = half_tr + disc, mu2 = half_tr - disc;
+    cplx mu = (std::abs(mu1 - d) < std::abs(mu2 - d)) ? mu1 : mu2;
+    if (iter % 11 == 10) mu = d + 0.75 * std::abs(c);  // exceptional shift
+    for (int k = l; k <= hi; ++k) at(k, k) -= mu;
+    std::vector<cplx> cs(hi - l), sn(hi - l);
+    for (int k = l; k < hi; ++k) {  // R = [[conj c, conj s], [-s, c]] zeroes (k+1, k)
+      const cplx x = at(k, k), y = at(k + 1, k);
+      const double r = std::sqrt(std::norm(x) + std::norm(y));
+      const cplx cc = r > 0 ? x / r : cplx(1.0), ss = r > 0 ? y / r : cplx(0.0);
+      cs[k - l] = cc;
+      sn[k - l] = ss;
+      for (int col = k; col <= hi; ++col) {
+        const cplx p = at(k, col), q = at(k + 1, col);
+        at(k, col) = std::conj(cc) * p + std::conj(ss) * q;
+        at(k + 1, col) = -ss * p + cc * q;
+      }
+    }
+    for (int k = l; k < hi; ++k) {  // right-multiply by R^H on columns (k, k+1)
+      const cplx cc = cs[k - l], ss = sn[k - l];
+      for (int row = l; row <= std::min(k + 1, hi); ++row) {
+        const cplx p = at(row, k), q = at(row, k + 1);
+        at(row, k) = p * cc + q * ss;
+        at(row, k + 1) = -p * std::conj(ss) + q * std::conj(cc);
+      }
+    }
+    for (int k = l; k <= hi; ++k) at(k, k) += mu;
+  }
+  return true;
+}
+
+bool hess_eigvec(int m, const std::vector<double>& H, cplx lam, std::vector<cplx>& y) {
+  double hnorm = 0.0;
+  for (double x : H) hnorm = std::max(hnorm, std::fabs(x));
+  const cplx shift = lam + cplx(1e-13 * std::max(hnorm, 1.0), 0.0);
+  std::vector<cplx> A((size_t)m * m);
+  for (int r = 0; r < m; ++r)
+    for (int c = 0; c < m; ++c) A[(size_t)r * m + c] = H[(size_t)r * m + c] - (r == c ? shift : cplx(0.0));
+  std::vector<int> piv(m);
+  for (int k = 0; k < m; ++k) {  // LU with partial pivoting
+    int p = k;
+    for (int r = k + 1; r < m; ++r)
+      if (std::abs(A[(size_t)r * m + k]) > std::abs(A[(size_t)p * m + k])) p = r;
+    piv[k] = p;
+    if (p != k)
+      for (int c = 0; c < m; ++c) std::swap(A[(size_t)k * m + c], A[(size_t)p * m + c]);
+    if (std::abs(A[(size_t)k * m + k]) == 0.0) A[(size_t)k * m + k] = 1e-300;
+    for (int r = k + 1; r < m; ++r) {
+      const cplx f = A[(size_t)r * m + k] / A[(size_t)k * m + k];
+      A[(size_t)r * m + k] = f;
+      for (int c = k + 1; c < m; ++c) A[(size_t)r * m + c] -= f * A[(size_t)k * m + c];
+    }
+  }
+  y.assign(m, cplx(1.0));
+  for (int it = 0; it < 3; ++it) {
+    std::vector<cplx> z(y);
+    for (int k = 0; k < m; ++k) std::swap(z[k], z[piv[k]]);
+    for (int r = 0; r < m; ++r)
+      for (int c = 0; c < r; ++c) z[r] -= A[(size_t)r * m + c] * z[c];
+    for (int r = m - 1; r >= 0; --r) {
+      for (int c = r + 1; c < m; ++c) z[r] -= A[(size_t)r * m + c] * z[c];
+      z[r] /= A[(size_t)r * m + r];
+    }
+    double nrm = 0.0;
+    for (const cplx& v : z) nrm += std::norm(v);
+    nrm = std::sqrt(nrm);
+    if (!(nrm > 0.0) || !std::isfinite(nrm)) return false;
+    for (int r = 0; r < m; ++r) y[r] = z[r] / nrm;
+  }
+  int big = 0;
+  for (int r = 1; r < m; ++r)
+    if (std::abs(y[r]) > std::abs(y[big])) big = r;
+  const cplx ph = std::conj(y[big]) / std::abs(y[big]);
+  for (cplx& v : y) v *= ph;
+  return true;
+}
+
+void shifted_qr_step(int m, std::vector<double>& H, std::vector<double>& Q, double re, double im, bool pair) {
+  auto h = [&](int r, int c) -> double& { return H[(size_t)r * m + c]; };
+  std::vector<double> M((size_t)m * m);
+  for (int r = 0; r < m; ++r)
+    for (int c = 0; c < m; ++c) {
+      double v = 0.0;
+      if (pair) {
+        for (int t = 0; t < m; ++t) v += h(r, t) * h(t, c);
+        v -= 2.0 * re * h(r, c);
+        if (r == c) v += re * re + im * im;
+      } else {
+        v = h(r, c) - (r == c ? re : 0.0);
+      }
+      M[(size_t)r * m + c] = v;
+    }
+  // Householder QR of M, accumulating Qs (m x m)
+  std::vector<double> Qs((size_t)m * m, 0.0);
+  for (int r = 0; r < m; ++r) Qs[(size_t)r * m + r] = 1.0;
+  std::vector<double> v(m);
+  for (int k = 0; k < m - 1; ++k) {
+    double nrm = 0.0;
+    for (int r = k; r < m; ++r) nrm += M[(size_t)r * m + k] * M[(size_t)r * m + k];
+    nrm = std::sqrt(nrm);
+    if (nrm == 0.0) continue;
+    const double x0 = M[(size_t)k * m + k];
+    const double alpha = (x0 >= 0.0) ? -nrm : nrm;
+    double vv = 0.0;
+    for (int r = k; r < m; ++r) {
+      v[r] = M[(size_t)r * m + k] - (r == k ? alpha : 0.0);
+      vv += v[r] * v[r];
+    }
+    if (vv == 0.0) continue;
+    for (int c = k; c < m; ++c) {  // M <- (I - 2 v v^T / v^T v) M
+      double s = 0.0;
+      for (int r = k; r < m; ++r) s += v[r] * M[(size_t)r * m + c];
+      s *= 2.0 / vv;
+      for (int r = k; r < m; ++r) M[(size_t)r * m + c] -= s * v[r];
+    }
+    for (int r = 0; r < m; ++r) {  // Qs <- Qs (I - 2 v v^T / v^T v)
+      double s = 0.0;
+      for (int c = k; c < m; ++c) s += Qs[(size_t)r * m + c] * v[c];
+      s *= 2.0 / vv;
+      for (int c = k; c < m; ++c) Qs[(size_t)r * m + c] -= s * v[c];
+    }
+  }
+  // H <- Qs^T H Qs ; Q <- Q Qs
+  std::vector<double> T((size_t)m * m, 0.0), Hn((size_t)m * m, 0.0), Qn((size_t)m * m, 0.0);
+  for (int r = 0; r < m; ++r)
+    for (int c = 0; c < m; ++c) {
+      double s = 0.0;
+      for (int t = 0; t < m; ++t) s += h(r, t) * Qs[(size_t)t * m + c];
+      T[(size_t)r * m + c] = s;
+    }
+  for (int r = 0; r < m; ++r)
+    for (int c = 0; c < m; ++c) {
+      double s = 0.0;
+      for (int t = 0; t < m; ++t) s += Qs[(size_t)t * m + r] * T[(size_t)t * m + c];
+      Hn[(size_t)r * m + c] = (r > c + 1) ? 0.0 : s;
+    }
+  for (int r = 0; r < m; ++r)
+    for (int c = 0; c < m; ++c) {
+      double s = 0.0;
+      for (int t = 0; t < m; ++t) s += Q[(size_t)r * m + t] * Qs[(size_t)t * m + c];
+      Qn[(size_t)r * m + c] = s;
+    }
+  H.swap(Hn);
+  Q.swap(Qn);
+}
+
 bool neumann_modes(int n, const double* d, const double* dd, std::vector<double>& lam, std::vector<double>& S,
                    std::vector<double>& Wf) {
   // K: couplings 1/dd on interior faces; M = diag(d).  T = M^-1/2 K M^-1/2.

@@ -1,9 +1,28 @@
 // Small dense host linear algebra used at set-up and by the Krylov drivers.
 #pragma once
 
+#include <complex>
 #include <vector>
 
 namespace lk {
+
+using cplx = std::complex<double>;
+
+// Eigenvalues of a real m x m matrix in upper Hessenberg form (row-major), by
+// the shifted QR iteration in complex arithmetic (Wilkinson shifts, deflation of
+// negligible subdiagonal entries).  Returns false if it fails to converge.
+bool hess_eigvals(int m, const std::vector<double>& H, std::vector<cplx>& lam);
+
+// Unit eigenvector y of H for eigenvalue lam by inverse iteration with a complex
+// LU factorization (partial pivoting); the largest-modulus entry is made real
+// positive.
+bool hess_eigvec(int m, const std::vector<double>& H, cplx lam, std::vector<cplx>& y);
+
+// One shifted QR step on H (m x m, Hessenberg) in real arithmetic: with
+// M = H - re I (single real shift) or M = H^2 - 2 re H + (re^2 + im^2) I (complex
+// pair), M = Qs R, H <- Qs^T H Qs and Q <- Q Qs (Q is m x m, row-major).  Entries
+// below the subdiagonal are reset to zero afterwards.
+void shifted_qr_step(int m, std::vector<double>& H, std::vector<double>& Q, double re, double im, bool pair);
 
 // Eigen-decomposition of the symmetric tridiagonal matrix with diagonal a[0..n-1]
 // and off-diagonal b[0..n-2]: T = Q diag(lam) Q^T, lam ascending, Q row-major

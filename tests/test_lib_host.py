@@ -70,3 +70,15 @@ def test_axis_modes_rejects_bad_faces():
     out = np.zeros(9)
     p = lambda a: a.ctypes.data_as(C.c_void_p)
     assert lib.lc_axis_modes(3, p(xf), p(out), p(out), p(out)) == -1
+
+
+@pytest.mark.parametrize("m,seed", [(1, 0), (5, 1), (20, 2), (60, 3)])
+def test_hessenberg_eigvals_match_numpy(m, seed):
+    lib = _lib()
+    rng = np.random.default_rng(seed)
+    H = np.triu(rng.standard_normal((m, m)), -1)
+    re = np.zeros(m); im = np.zeros(m)
+    p = lambda a: a.ctypes.data_as(C.c_void_p)
+    assert lib.lc_hessenberg_eigvals(m, p(np.ascontiguousarray(H)), p(re), p(im)) == 0
+    from oracle.eigen import match_distance
+    assert match_distance(np.linalg.eigvals(H), re + 1j * im) < 1e-10 * max(1.0, np.abs(H).max())

@@ -158,6 +158,11 @@ def main():
     U = synthetic_base_flow(ctx, torch)
     ctx.set_base_flow(U)
     inputs = make_inputs(ctx, torch, a.warmup + a.steps)
+    # calibration for hardware byte counters: one plain device copy of 256 MiB
+    calib = torch.empty(1 << 25, dtype=torch.float64, device="cuda")
+    calib.copy_(inputs[0][: 1].expand(1 << 25))
+    torch.empty_like(calib).copy_(calib)
+    del calib
     torch.cuda.synchronize()
 
     forms = {}

@@ -100,44 +100,62 @@ def relu(x):
     return np.maximum(x, 0.0)
 
 
-def forward(p, x):
-    """Network output y ([D][H][W][1]) and the cache for backward."""
+def _ident(a):
+    return a
+
+
+def forward(p, x, q=None):
+    """Network output y ([D][H][W][1]) and the cache for backward.  q (default:
+    identity) is applied to every stored activation: passing a rounding to a
+    narrower format reproduces a network that keeps its activations in it."""
+    q = q or _ident
     c = {"x": x}
-    c["e1"] = relu(conv(x, p["enc1.w"], p["enc1.b"]))
-    c["p1"] = pool(c["e1"])
-    c["e2"] = relu(conv(c["p1"], p["enc2.w"], p["enc2.b"]))
-    c["p2"] = pool(c["e2"])
-    c["bt"] = relu(conv(c["p2"], p["bott.w"], p["bott.b"]))
+    c["e1"] = q(relu(conv(x, p["enc1.w"], p["enc1.b"])))
+    c["p1"] = q(pool(c["e1"]))
+    c["e2"] = q(relu(conv(c["p1"], p["enc2.w"], p["enc2.b"])))
+    c["p2"] = q(pool(c["e2"]))
+    c["bt"] = q(relu(conv(c["p2"], p["bott.w"], p["bott.b"])))
     c["c2"] = np.concatenate([up(c["bt"]), c["e2"]], axis=3)
-    c["d2"] = relu(conv(c["c2"], p["dec2.w"], p["dec2.b"]))
+    c["d2"] = q(relu(conv(c["c2"], p["dec2.w"], p["dec2.b"])))
     c["c1"] = np.concatenate([up(c["d2"]), c["e1"]], axis=3)
-    c["d1"] = relu(conv(c["c1"], p["dec1.w"], p["dec1.b"]))
+    c["d1"] = q(relu(conv(c["c1"], p["dec1.w"], p["dec1.b"])))
     y = conv(c["d1"], p["head.w"], p["head.b"])
     return y, c
 
 
-def loss_and_grad(p, x, target):
-    """Mean squared error and its gradient with respect to every parameter and x."""
-    y, c = forward(p, x)
+def loss_and_grad(p, x, target, q=None):
+    """Mean squared error and its gradient with respect to every parameter and x.
+    q as in forward, applied also to the gradients that enter a convolution's
+    backward pass (the masked output gradients)."""
+    q = q or _ident
+    y, c = forward(p, x, q)
     n = y.size
     loss = float(np.sum((y - target) ** 2) / n)
     dy = 2.0 * (y - target) / n
     g = {}
     dd1, g["head.w"], g["head.b"] = conv_backward(c["d1"], p["head.w"], dy)
-    dd1 = dd1 * (c["d1"] > 0)
+    dd1 = q(dd1 * (c["d1"] > 0))
     dc1, g["dec1.w"], g["dec1.b"] = conv_backward(c["c1"], p["dec1.w"], dd1)
-    dd2 = up_backward(dc1[..., :32]) * (c["d2"] > 0)
+    dd2 = q(up_backward(dc1[..., :32]) * (c["d2"] > 0))
     de1 = dc1[..., 32:]
     dc2, g["dec2.w"], g["dec2.b"] = conv_backward(c["c2"], p["dec2.w"], dd2)
-    dbt = up_backward(dc2[..., :64]) * (c["bt"] > 0)
+    dbt = q(up_backward(dc2[..., :64]) * (c["bt"] > 0))
     de2 = dc2[..., 64:]
     dp2, g["bott.w"], g["bott.b"] = conv_backward(c["p2"], p["bott.w"], dbt)
-    de2 = (de2 + pool_backward(dp2)) * (c["e2"] > 0)
+    de2 = q((de2 + pool_backward(dp2)) * (c["e2"] > 0))
     dp1, g["enc2.w"], g["enc2.b"] = conv_backward(c["p1"], p["enc2.w"], de2)
-    de1 = (de1 + pool_backward(dp1)) * (c["e1"] > 0)
+    de1 = q((de1 + pool_backward(dp1)) * (c["e1"] > 0))
     dx, g["enc1.w"], g["enc1.b"] = conv_backward(c["x"], p["enc1.w"], de1)
     g["x"] = dx
     return loss, g
+
+
+def bf16(a):
+    """Round to the nearest bfloat16 (ties to even), returned as float64."""
+    f = np.ascontiguousarray(a, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64).reshape(np.shape(a))
 
 
 def adam(p, g, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
@@ -189,14 +207,17 @@ def targets(g: Grid, phi):
     return t
 
 
-def guess(g: Grid, p, w):
+def guess(g: Grid, p, w, q=None):
     """Learned initial correction phi0 = c y for SIMPLE's first pass, where y is
     the network output on the physical cells and c minimises the V-weighted
     continuity residual |r - c D G y| (r = D w).  Returns (phi0, eps) with
-    eps = |r - D G phi0|_V / |r|_V <= 1; phi0 = 0 (eps = 1) when the fit is void."""
+    eps = |r - D G phi0|_V / |r|_V <= 1; phi0 = 0 (eps = 1) when the fit is void.
+    q: rounding of the network input and activations, as in forward."""
     x, r = features(g, w)
     nz, ny, nx = r.shape
-    y = forward(p, x)[0][:nz, :ny, :nx, 0]
+    if q is not None:
+        x = q(x)
+    y = forward(p, x, q)[0][:nz, :ny, :nx, 0]
     z = fv.divergence(g, fv.gradient(g, y))
     zz = _vdot(g, z, z)
     rr = _vdot(g, r, r)

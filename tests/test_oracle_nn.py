@@ -198,7 +198,7 @@ def test_guess_fit_recovers_exact_solution(monkeypatch):
     phi = PoissonFD(g).solve(r)
     scale = -2.5
 
-    def fake(p, x):
+    def fake(p, x, q=None):
         y = np.zeros(x.shape[:3] + (1,))
         y[:4, :5, :6, 0] = scale * phi
         return y, None
@@ -210,3 +210,29 @@ def test_guess_fit_recovers_exact_solution(monkeypatch):
     p = nn.init_params(1)
     phi0, eps = nn.guess(g, p, w)
     assert 0.0 < eps <= 1.0
+
+
+def test_bf16_rounding_closed_forms():
+    # representable values stay, halfway cases go to even, one ulp of 1 is 2^-7
+    vals = np.array([1.0, -2.5, 1.0 + 2 ** -7, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, 3.0e38, 1e-40])
+    r = nn.bf16(vals)
+    assert r[0] == 1.0 and r[1] == -2.5 and r[2] == 1.0 + 2 ** -7
+    assert r[3] == 1.0 and r[4] == 1.0 + 2 ** -6
+    assert abs(r[5] - 3.0e38) / 3.0e38 < 2 ** -8
+    x = rnd(1000, 23)
+    assert np.max(np.abs(nn.bf16(x) - x) / np.abs(x)) <= 2 ** -8
+
+
+def test_rounded_network_close_to_exact():
+    """The rounding hook only perturbs: with BF16 storage the loss gradient stays
+    within a few percent of the exact one, with the identity it is the same."""
+    p = nn.init_params(6)
+    x = rnd((8, 8, 8, 4), 24)
+    t = rnd((8, 8, 8, 1), 25)
+    l0, g0 = nn.loss_and_grad(p, x, t)
+    l1, g1 = nn.loss_and_grad(p, x, t, q=lambda a: a)
+    assert l0 == l1 and all(np.array_equal(g0[k], g1[k]) for k in g0)
+    l2, g2 = nn.loss_and_grad(p, x, t, q=nn.bf16)
+    assert abs(l2 - l0) < 1e-2 * l0
+    for k in ("head.w", "dec1.w", "enc1.w"):
+        assert np.linalg.norm(g2[k] - g0[k]) < 0.1 * np.linalg.norm(g0[k])

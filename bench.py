@@ -5,9 +5,13 @@ SIMPLE projection (divergence, tensor-product pressure-correction solve,
 velocity/pressure correction, divergence certificate) to a relative divergence
 residual rho <= 1e-8, on a 200^3 tanh-stretched grid (centre/wall spacing 10),
 Re = 1900, lid along x.  Inputs are seeded (SplitMix64) and resident in HBM
-before the timed region.
+before the timed region.  Three forms: plain FP64, mixed (FP32 solves inside
+FP64 refinement) and learned (a BF16 U-Net's guess of the first correction,
+trained beforehand on a 64^3 grid with pairs the method generates, then mixed
+passes).
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--size 200] [--no-cpu]
+                    [--train-steps 300]
 """
 from __future__ import annotations
 
@@ -22,6 +26,10 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 PEAK_FP64_VECTOR_TFLOPS = 78.6
+PEAK_BF16_TFLOPS = 2500.0
+# multiply-adds x 2 per voxel of the network's padded grid: 3x3x3 convs 4->16, 16->32 (1/8 of
+# the voxels), 32->64 (1/64), 96->32 (1/8), 48->16, and the 16->1 head
+NN_FLOP_PER_VOXEL = 2.0 * (27 * 4 * 16 + 27 * 16 * 32 / 8 + 27 * 32 * 64 / 64 + 27 * 96 * 32 / 8 + 27 * 48 * 16 + 16)
 RE = 1900.0
 TANH_RATIO = 10.0
 
@@ -34,6 +42,8 @@ def parse():
     ap.add_argument("--size", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-sample", type=int, default=2, help="oracle Krylov vectors timed on the host")
+    ap.add_argument("--train-steps", type=int, default=300, help="Adam steps of the learned guess (64^3 pairs)")
+    ap.add_argument("--train-size", type=int, default=64)
     return ap.parse_args()
 
 
@@ -69,16 +79,35 @@ def time_form(ctx, torch, inputs, warmup, steps, precision):
     for q in range(warmup):
         ctx.krylov_vector(inputs[q % len(inputs)], vo, po, precision=precision, tol=1e-8)
     torch.cuda.synchronize()
-    iters = []
+    stats = []
     t0 = time.perf_counter()
     for q in range(steps):
         _, _, st = ctx.krylov_vector(inputs[warmup + q], vo, po, precision=precision, tol=1e-8)
         if not st["converged"]:
             raise RuntimeError(f"step {q} did not converge: {st}")
-        iters.append(st["iterations"])
+        stats.append(st)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    return dt, iters
+    return dt, stats
+
+
+def train_guess(lk, torch, n, steps):
+    """The learned guess, trained on an n^3 tanh-10 grid at the same Re (seeded
+    synthetic base flow; pairs = the method's first SIMPLE corrections)."""
+    tctx = lk.Context(n, n, n)
+    tctx.set_stretching("tanh", TANH_RATIO)
+    tctx.set_re(RE)
+    tctx.set_lid(0.0)
+    tctx.set_base_flow(synthetic_base_flow(tctx, torch))
+    net = lk.Net(seed=11)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = net.train(tctx, steps=steps, lr=2e-3, seed=7)
+    dt = time.perf_counter() - t0
+    tctx.close()
+    return net, {"train_grid": f"{n}^3 tanh-10", "steps": steps, "seconds": dt,
+                 "loss_first10": float(sum(hist[:10]) / max(1, min(10, steps))),
+                 "loss_last30": float(sum(hist[-30:]) / max(1, min(30, steps)))}
 
 
 def kernel_table(prof, n):
@@ -165,13 +194,32 @@ def main():
     del calib
     torch.cuda.synchronize()
 
+    log(f"[bench] training the learned guess: {a.train_steps} steps on {a.train_size}^3")
+    net, training = train_guess(lk, torch, a.train_size, a.train_steps)
+    ctx.set_net(net)
+    log(f"[bench] trained in {training['seconds']:.1f} s, loss {training['loss_first10']:.3f} -> "
+        f"{training['loss_last30']:.3f}")
+
     forms = {}
-    for name, prec in (("plain", lk.FP64), ("mixed", lk.MIXED)):
-        dt, iters = time_form(ctx, torch, inputs, a.warmup, a.steps, prec)
+    outs = {}
+    for name, prec in (("plain", lk.FP64), ("mixed", lk.MIXED), ("learned", lk.LEARNED)):
+        dt, stats = time_form(ctx, torch, inputs, a.warmup, a.steps, prec)
+        iters = [st["iterations"] for st in stats]
         forms[name] = {"value": a.steps / dt, "ms_per_step": 1e3 * dt / a.steps,
-                       "simple_passes_mean": sum(iters) / len(iters)}
+                       "simple_passes_mean": sum(iters) / len(iters),
+                       "rho_first_pass_mean": sum(st["rho_hist"][0] for st in stats) / len(stats)}
+        if name == "learned":
+            forms[name]["guess_used"] = sum(st["guess_used"] for st in stats)
+            forms[name]["guess_eps_mean"] = sum(st["guess_eps"] for st in stats) / len(stats)
+            forms[name]["training"] = training
+            forms[name]["passes"] = "mixed"
+        outs[name], _, _ = ctx.krylov_vector(inputs[0], precision=prec, tol=1e-8)
         log(f"[bench] {name}: {forms[name]['value']:.1f} vectors/s, {forms[name]['ms_per_step']:.3f} ms/step, "
             f"passes {forms[name]['simple_passes_mean']:.2f}")
+    ref = outs["plain"]
+    for name in ("mixed", "learned"):
+        forms[name]["rel_diff_vs_plain"] = float(torch.linalg.vector_norm(outs[name] - ref) /
+                                                 torch.linalg.vector_norm(ref))
 
     # profiled repeat of the plain timed loop: per-kernel HIP events on the context stream
     ctx.profile(True)
@@ -179,6 +227,18 @@ def main():
     prof = ctx.profile_read()
     ctx.profile(False)
     table = kernel_table(prof, n)
+    # the learned form's network forward pass (all layers), same method
+    ctx.profile(True)
+    time_form(ctx, torch, inputs, 0, min(a.steps, 5), lk.LEARNED)
+    lprof = ctx.profile_read()
+    ctx.profile(False)
+    if "nn_forward" in lprof:
+        ms, launches = lprof["nn_forward"]
+        avg = ms / launches
+        flops = NN_FLOP_PER_VOXEL * (((n + 3) // 4 * 4) ** 3)
+        forms["learned"]["nn_forward"] = {"avg_ms": avg, "launches": launches, "TFLOP/s": flops / (avg * 1e-3) / 1e12,
+                                          "frac_bf16_mfma": flops / (avg * 1e-3) / 1e12 / PEAK_BF16_TFLOPS,
+                                          "algorithmic_flop": flops}
     dom = max((k for k in table if "algorithmic" in table[k]), key=lambda k: table[k]["total_ms"])
     d = table[dom]
     if "TFLOP/s" in d:

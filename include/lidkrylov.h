@@ -53,11 +53,14 @@ extern "C" {
 /* Precision forms of the pressure-correction solve. */
 #define LC_FP64 0  /* plain: every step in float64                            */
 #define LC_MIXED 1 /* float32 tensor-product solves inside float64 refinement */
+#define LC_LEARNED 2 /* network guess of the first correction, then LC_MIXED  */
+                     /* passes (needs lc_set_net; plain fallback, see below) */
 
 /* Pressure-correction Poisson solvers. */
 #define LC_POISSON_TP 0 /* full tensor-product factorization (default)        */
 
 typedef struct lc_ctx lc_ctx;
+typedef struct lc_net lc_net;
 
 typedef struct {
   int iterations;     /* SIMPLE passes (projection corrections) performed      */
@@ -65,6 +68,9 @@ typedef struct {
   double rho0;        /* |D w|_V, the divergence of the uncorrected vector     */
   double rho_hist[16];/* rho after each pass                                   */
   double ms_total;    /* wall time of the call, host clock                     */
+  int guess_used;     /* LC_LEARNED: 1 if the network guess started the loop,  */
+                      /* 0 if it fell back to the plain start v = w, p = 0     */
+  double guess_eps;   /* LC_LEARNED: rho right after the guess (1 on fallback) */
 } lc_stats;
 
 /* Library version string (static storage). */
@@ -206,6 +212,70 @@ int lc_arnoldi_leading(lc_ctx* ctx, int k, int m, double tol, int max_restarts, 
                        int precision, double proj_tol, double* eig_re, double* eig_im, double* resid,
                        double* vec_re, double* vec_im, int* n_out, long* n_vectors);
 
+/* ------------------------------------------------- learned correction guess */
+
+/* Not part of the paper's method: a small 3D convolutional network (3-level
+ * U-Net, 3x3x3 kernels, channels 4-16-32-64, 2x2x2 average pooling, nearest
+ * upsampling with skip concatenation, ReLU, 1x1x1 head) that guesses the first
+ * pressure correction of the SIMPLE loop (Section 3, step 1) from the momentum
+ * update w.  Input channels on the cells: w averaged to cell centres (3) and
+ * D w, each group divided by its volume-weighted RMS; the grid is zero-padded
+ * to multiples of 4.  Weights and activations are BF16 on the matrix cores
+ * with FP32 accumulation; FP32 master weights and Adam moments.
+ *
+ * In the LC_LEARNED form the output y is scaled by the s minimising
+ * |D w - s D G y|_V, the loop starts from v = w - G (s y), p = s y and then
+ * runs LC_MIXED passes to the tolerance.  If the scaled guess would not lower
+ * the divergence by at least 0.1% (or the fit is void) the loop starts plainly
+ * from v = w, p = 0 (stats.guess_used = 0): the network can cost time but never
+ * changes the fixed point.
+ *
+ * Parameters (host order, float32): for each layer enc1, enc2, bottleneck,
+ * dec2, dec1, head the weights W[cout][taps][cin] (taps 27, tap = (dz+1)*9 +
+ * (dy+1)*3 + (dx+1), cross-correlation) then the biases b[cout];
+ * lc_net_param_count() values in total.  A network is used on one stream at
+ * a time; its activation memory grows on demand and is freed by lc_net_destroy. */
+long lc_net_param_count(void);
+
+/* Create a network with He-normal weights (SplitMix64 stream `seed`, Box-Muller)
+ * and zero biases on the current device.  LC_ENOMEM on allocation failure. */
+int lc_net_create(lc_net** out, uint64_t seed);
+int lc_net_destroy(lc_net* net);
+const char* lc_net_last_error(const lc_net* net);
+
+/* Copy the float32 master parameters out of / into the network (host arrays of
+ * lc_net_param_count() floats).  Setting resets the Adam state. */
+int lc_net_get_params(lc_net* net, float* host);
+int lc_net_set_params(lc_net* net, const float* host);
+
+/* Forward pass on a D x H x W grid (each a positive multiple of 4):
+ * x (device float32 [D][H][W][4]) -> y (device float32 [D][H][W]).
+ * hip_stream: hipStream_t (NULL = default).  Returns when y is valid. */
+int lc_net_forward(lc_net* net, void* hip_stream, const float* x, float* y, int D, int H, int W);
+
+/* Mean squared error of the output against t (device float32 [D][H][W]) and
+ * its gradient; grad_host (may be NULL) receives the lc_net_param_count()
+ * gradients in parameter order; if lr > 0 one Adam step (beta 0.9, 0.999,
+ * eps 1e-8) follows.  loss (host, may be NULL). */
+int lc_net_step(lc_net* net, void* hip_stream, const float* x, const float* t, int D, int H, int W, double lr,
+                double* loss, float* grad_host);
+
+/* Attach a network to a context for LC_LEARNED (NULL detaches; not owned). */
+int lc_set_net(lc_ctx* ctx, lc_net* net);
+
+/* Train on pairs the method generates on the context's grid, base flow and Re:
+ * per step a seeded random velocity (SplitMix64 stream seed * 1000003 + step) is
+ * projected (float64) to v, w = L_U v, and the target is the first SIMPLE
+ * correction phi of w (the float64 tensor-product solve of (D G) phi = D w),
+ * scaled by its volume-weighted RMS; one Adam step of learning rate lr.
+ * loss_hist (host, may be NULL): `steps` losses. */
+int lc_net_train(lc_ctx* ctx, lc_net* net, int steps, double lr, uint64_t seed, double* loss_hist);
+
+/* The scaled network guess phi0 (cell, device) for the momentum update w
+ * (velocity, device) with the attached network, and eps (host, may be NULL) =
+ * |D w - D G phi0|_V / |D w|_V.  On fallback phi0 = 0 and eps = 1. */
+int lc_learned_guess(lc_ctx* ctx, const double* w, double* phi0, double* eps);
+
 /* ---------------------------------------------------------- vector helpers */
 
 /* Euclidean dot product of two velocity vectors (host result). */
@@ -225,7 +295,9 @@ int lc_dot(lc_ctx* ctx, const double* a, const double* b, double* out);
 #define LC_K_REDUCE 8     /* fixed-order final reductions                    */
 #define LC_K_CAST 9       /* float64 <-> float32 conversions                 */
 #define LC_K_VECTOR 10    /* dot / axpy / scale / fill                       */
-#define LC_K_COUNT 11
+#define LC_K_NN_FORWARD 11 /* network forward pass (all layers)              */
+#define LC_K_NN_MISC 12   /* network input/output conversions and fits       */
+#define LC_K_COUNT 13
 
 /* Enable (1) or disable (0) per-launch HIP-event timing on the context's
  * stream; enabling clears previous records.  Adds two event records per

@@ -10,9 +10,9 @@ import ctypes as C
 import numpy as np
 
 from . import _lib
-from ._lib import FP64, MIXED, SINE, TANH, UNIFORM, LidKrylovError, Stats  # noqa: F401
+from ._lib import FP64, LEARNED, MIXED, SINE, TANH, UNIFORM, LidKrylovError, Stats  # noqa: F401
 
-__all__ = ["Context", "FP64", "MIXED", "UNIFORM", "SINE", "TANH", "LidKrylovError"]
+__all__ = ["Context", "Net", "FP64", "MIXED", "LEARNED", "UNIFORM", "SINE", "TANH", "LidKrylovError"]
 
 
 def _torch():
@@ -43,6 +43,8 @@ class Context:
         self.ncell = int(self.lib.lc_cell_size(h))
 
     # ------------------------------------------------------------- helpers
+    net = None
+
     def _check(self, rc, allow_notconv=False):
         if rc == 0 or (allow_notconv and rc == _lib.LC_ENOTCONV):
             return rc
@@ -206,6 +208,20 @@ class Context:
         return out
 
     # ----------------------------------------------------------- profiling
+    # ------------------------------------------------------ learned guess
+    def set_net(self, net):
+        """Attach a Net for the LEARNED form (None detaches)."""
+        self._check(self.lib.lc_set_net(self._h, net._h if net is not None else None))
+        self.net = net
+
+    def learned_guess(self, w, out=None):
+        """(phi0, eps): the scaled network guess of the first correction of w."""
+        out = self.cells() if out is None else out
+        eps = C.c_double()
+        self._check(self.lib.lc_learned_guess(self._h, self._ptr(w, self.nvel, "w"),
+                                              self._ptr(out, self.ncell, "phi0"), C.byref(eps)))
+        return out, eps.value
+
     def profile(self, on=True):
         self._check(self.lib.lc_profile_enable(self._h, 1 if on else 0))
 
@@ -224,3 +240,78 @@ class Context:
         self._check(self.lib.lc_dot(self._h, self._ptr(a, self.nvel, "a"), self._ptr(b, self.nvel, "b"),
                                     C.byref(out)))
         return out.value
+
+
+class Net:
+    """The learned pressure-correction guess (3-level 3D U-Net, BF16 matrix cores)."""
+
+    def __init__(self, seed: int = 0):
+        self.lib = _lib.load()
+        h = C.c_void_p()
+        rc = self.lib.lc_net_create(C.byref(h), seed)
+        if rc != 0:
+            raise LidKrylovError(rc, "lc_net_create failed")
+        self._h = h
+        self.nparams = int(self.lib.lc_net_param_count())
+
+    def _check(self, rc):
+        if rc != 0:
+            raise LidKrylovError(rc, self.lib.lc_net_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.lib.lc_net_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self):
+        out = np.zeros(self.nparams, dtype=np.float32)
+        self._check(self.lib.lc_net_get_params(self._h, out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.size != self.nparams:
+            raise ValueError(f"need {self.nparams} parameters")
+        self._check(self.lib.lc_net_set_params(self._h, p.ctypes.data_as(C.c_void_p)))
+
+    @staticmethod
+    def _f32(t, shape, name):
+        torch = _torch()
+        if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name}: need a contiguous float32 CUDA tensor of shape {tuple(shape)}")
+        return C.c_void_p(t.data_ptr())
+
+    def forward(self, x, stream=None):
+        """x: [D][H][W][4] float32 CUDA tensor -> y [D][H][W]."""
+        torch = _torch()
+        D, H, W, _ = x.shape
+        y = torch.empty((D, H, W), dtype=torch.float32, device=x.device)
+        s = stream if stream is not None else torch.cuda.current_stream()
+        self._check(self.lib.lc_net_forward(self._h, C.c_void_p(s.cuda_stream), self._f32(x, (D, H, W, 4), "x"),
+                                            C.c_void_p(y.data_ptr()), D, H, W))
+        return y
+
+    def step(self, x, t, lr=0.0, grads=False, stream=None):
+        """MSE loss of forward(x) against t, optional gradients (host) and Adam step."""
+        torch = _torch()
+        D, H, W, _ = x.shape
+        s = stream if stream is not None else torch.cuda.current_stream()
+        g = np.zeros(self.nparams, dtype=np.float32) if grads else None
+        loss = C.c_double()
+        self._check(self.lib.lc_net_step(self._h, C.c_void_p(s.cuda_stream), self._f32(x, (D, H, W, 4), "x"),
+                                         self._f32(t, (D, H, W), "t"), D, H, W, lr, C.byref(loss),
+                                         g.ctypes.data_as(C.c_void_p) if grads else None))
+        return (loss.value, g) if grads else loss.value
+
+    def train(self, ctx: "Context", steps: int, lr: float = 1e-3, seed: int = 1):
+        """Adam steps on pairs the method generates on ctx's grid; returns the losses."""
+        hist = np.zeros(max(steps, 1), dtype=np.float64)
+        ctx._check(self.lib.lc_net_train(ctx._h, self._h, steps, lr, seed, hist.ctypes.data_as(C.c_void_p)))
+        return hist[:steps]
+

@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(HERE, "liblidkrylov.so")
 
 LC_OK, LC_ENOTCONV, LC_EINVAL, LC_ESTATE, LC_EHIP, LC_ENOMEM = 0, 1, -1, -2, -3, -4
 UNIFORM, SINE, TANH = 0, 1, 2
-FP64, MIXED = 0, 1
+FP64, MIXED, LEARNED = 0, 1, 2
 
 
 class LidKrylovError(RuntimeError):
@@ -24,12 +24,14 @@ class LidKrylovError(RuntimeError):
 
 class Stats(C.Structure):
     _fields_ = [("iterations", C.c_int), ("rho", C.c_double), ("rho0", C.c_double),
-                ("rho_hist", C.c_double * 16), ("ms_total", C.c_double)]
+                ("rho_hist", C.c_double * 16), ("ms_total", C.c_double), ("guess_used", C.c_int),
+                ("guess_eps", C.c_double)]
 
     def as_dict(self):
         n = min(self.iterations, 16)
         return {"iterations": self.iterations, "rho": self.rho, "rho0": self.rho0,
-                "rho_hist": [self.rho_hist[q] for q in range(n)], "ms_total": self.ms_total}
+                "rho_hist": [self.rho_hist[q] for q in range(n)], "ms_total": self.ms_total,
+                "guess_used": bool(self.guess_used), "guess_eps": self.guess_eps}
 
 
 _P = C.c_void_p
@@ -65,12 +67,23 @@ _SIGS = {
                             C.POINTER(_I)]),
     "lc_arnoldi_leading": (_I, [_P, _I, _I, _D, _I, C.c_ulonglong, _I, _D, _P, _P, _P, _P, _P, C.POINTER(_I),
                                 C.POINTER(C.c_long)]),
+    "lc_net_param_count": (C.c_long, []),
+    "lc_net_create": (_I, [C.POINTER(_P), C.c_uint64]),
+    "lc_net_destroy": (_I, [_P]),
+    "lc_net_last_error": (C.c_char_p, [_P]),
+    "lc_net_get_params": (_I, [_P, _P]),
+    "lc_net_set_params": (_I, [_P, _P]),
+    "lc_net_forward": (_I, [_P, _P, _P, _P, _I, _I, _I]),
+    "lc_net_step": (_I, [_P, _P, _P, _P, _I, _I, _I, _D, C.POINTER(_D), _P]),
+    "lc_set_net": (_I, [_P, _P]),
+    "lc_net_train": (_I, [_P, _P, _I, _D, C.c_uint64, _P]),
+    "lc_learned_guess": (_I, [_P, _P, _P, C.POINTER(_D)]),
     "lc_profile_enable": (_I, [_P, _I]),
     "lc_profile_read": (_I, [_P, _I, C.POINTER(_D), C.POINTER(C.c_long)]),
     "lc_profile_name": (C.c_char_p, [_I]),
 }
 KERNEL_CLASSES = ["momentum", "residual", "divergence", "correct", "tp_x", "tp_y", "tp_z", "eigscale",
-                  "reduce", "cast", "vector"]
+                  "reduce", "cast", "vector", "nn_forward", "nn_misc"]
 
 _lib = None
 

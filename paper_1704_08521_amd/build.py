@@ -13,7 +13,8 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "liblidkrylov.so")
-SOURCES = ["lk_stencil.hip", "lk_transform.hip", "lk_kernels.hip", "lk_api.cpp", "lk_krylov.cpp", "lk_linalg.cpp"]
+SOURCES = ["lk_stencil.hip", "lk_transform.hip", "lk_kernels.hip", "lk_nn.hip", "lk_api.cpp", "lk_krylov.cpp",
+           "lk_linalg.cpp", "lk_nn_host.cpp"]
 ARCH = os.environ.get("LK_OFFLOAD_ARCH", "gfx950")
 
 # -packed-fp32-ops: never emit packed FP32 arithmetic (v_pk_*_f32)

@@ -430,11 +430,14 @@ int lc_project(lc_ctx* c, const double* w, double* v, double* p, int precision, 
   int rc = check_ready(c);
   if (rc) return rc;
   if (!aligned(w) || !aligned(v) || !aligned(p) || v == w) return fail(c, LC_EINVAL, "bad pointers");
-  if (precision != LC_FP64 && precision != LC_MIXED) return fail(c, LC_EINVAL, "unknown precision");
+  if (precision != LC_FP64 && precision != LC_MIXED && precision != LC_LEARNED)
+    return fail(c, LC_EINVAL, "unknown precision");
+  if (precision == LC_LEARNED && !c->net) return fail(c, LC_ESTATE, "no network attached for the learned form");
   if (!(tol >= 0.0) || max_iter < 1) return fail(c, LC_EINVAL, "bad tolerance or iteration cap");
   lc_stats local{};
   lc_stats& S = st ? *st : local;
   std::memset(&S, 0, sizeof S);
+  S.guess_eps = 1.0;
   double n0 = 0.0;
   rc = vnorm_div(c, w, c->r, &n0);
   if (rc) return rc;
@@ -448,11 +451,33 @@ int lc_project(lc_ctx* c, const double* w, double* v, double* p, int precision, 
     S.ms_total = now_ms() - t0;
     return LC_OK;
   }
+  // Learned form: the network's correction starts the loop (v = w - G phi0, p = phi0),
+  // then mixed-precision passes; without gain it falls back to v = w, p = 0.
+  bool started = false;
+  const int pass_precision = precision == LC_LEARNED ? LC_MIXED : precision;
+  if (precision == LC_LEARNED) {
+    double fit = 1.0;
+    rc = learned_start(c, w, v, p, &started, &fit);
+    if (rc) return rc;
+    if (started) {
+      double nk = 0.0;
+      rc = vnorm_div(c, v, c->r, &nk);
+      if (rc) return rc;
+      S.guess_used = 1;
+      S.guess_eps = nk / n0;
+      if (!std::isfinite(S.guess_eps)) return fail(c, LC_EINVAL, "non-finite divergence after the learned guess");
+      S.rho = S.guess_eps;
+      if (S.rho <= tol) {
+        S.ms_total = now_ms() - t0;
+        return LC_OK;
+      }
+    }
+  }
   // SIMPLE loop (Section 3): v = w, p = 0; repeat {solve; v -= G phi; p += phi}
   for (int it = 0; it < max_iter; ++it) {
-    rc = poisson(c, c->r, c->phi, precision);
+    rc = poisson(c, c->r, c->phi, pass_precision);
     if (rc) return rc;
-    KLAUNCH(c, LC_K_CORRECT, launch_correct(c->g, w, c->phi, v, p, it > 0, c->stream));
+    KLAUNCH(c, LC_K_CORRECT, launch_correct(c->g, w, c->phi, v, p, started || it > 0, c->stream));
     double nk = 0.0;
     rc = vnorm_div(c, v, c->r, &nk);
     if (rc) return rc;
@@ -490,9 +515,9 @@ int lc_dot(lc_ctx* c, const double* a, const double* b, double* out) {
 
 }  // extern "C"
 
-static const char* kKernelNames[LC_K_COUNT] = {"momentum", "residual", "divergence", "correct",
-                                                "tp_x",     "tp_y",     "tp_z",       "eigscale",
-                                                "reduce",   "cast",     "vector"};
+static const char* kKernelNames[LC_K_COUNT] = {"momentum", "residual", "divergence", "correct",  "tp_x",
+                                                "tp_y",     "tp_z",     "eigscale",   "reduce",   "cast",
+                                                "vector",   "nn_forward", "nn_misc"};
 
 extern "C" const char* lc_profile_name(int k) { return (k >= 0 && k < LC_K_COUNT) ? kKernelNames[k] : nullptr; }
 

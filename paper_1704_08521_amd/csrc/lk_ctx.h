@@ -81,6 +81,7 @@ struct lc_ctx {
   double* dsmall = nullptr;  // kSmall doubles
   double* hsmall = nullptr;  // kSmall doubles, pinned
   double* pk = nullptr;      // cell
+  lc_net* net = nullptr;     // learned guess (not owned)
   bool prof = false;
   std::vector<Rec> recs;
   std::vector<hipEvent_t> ev_pool;
@@ -107,6 +108,8 @@ int poisson(lc_ctx* c, const double* r, double* phi, int precision);
 // Euclidean dot product / max |x| of velocity vectors, host results
 int vdot(lc_ctx* c, const double* a, const double* b, double* out);
 int vmaxabs(lc_ctx* c, const double* a, double* out);
+// learned start of the SIMPLE loop (see lk_nn_host.cpp); requires c->net
+int learned_start(lc_ctx* c, const double* w, double* v, double* p, bool* used, double* eps_fit);
 
 }  // namespace lk
 

@@ -1,0 +1,668 @@
+// Kernels of the learned pressure-correction guess: a 3-level 3D U-Net (3x3x3
+// convolutions, 2x2x2 average pooling, nearest upsampling with skip
+// concatenation, 1x1x1 head) in BF16 with FP32 accumulation on the CDNA4 matrix
+// cores, its backward pass, Adam, and the conversions between the FP64 fields of
+// the SIMPLE loop and the network tensors.
+//
+// Network tensors are channels-last, [D][H][W][C] (z, y, x, channel), BF16,
+// C a multiple of 8 so that one lane's 8 reduction values are one 16-byte load.
+// A 3x3x3 convolution is an implicit GEMM: rows = output voxels, columns = output
+// channels, reduction index k = tap * CIN + ci (tap = (dz+1)*9 + (dy+1)*3 + (dx+1)),
+// padded to a multiple of 32 with zero weights.  v_mfma_f32_16x16x32_bf16 lane
+// layout (lane l, g = l / 16): A row l%16, k = 8g..8g+7; B column l%16, same k;
+// result rows 4g..4g+3 of column l%16.
+#include <hip/hip_runtime.h>
+
+#include "lk_nn.h"
+
+namespace lk {
+namespace {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float floatx4;
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ bf16x8 load8(const bf16* p, bool ok) {
+  // branch-free guarded 16-byte load: the address is valid whenever ok is false
+  const u32x4 v = *reinterpret_cast<const u32x4*>(p);
+  u32x4 s;
+  s.x = ok ? v.x : 0u;
+  s.y = ok ? v.y : 0u;
+  s.z = ok ? v.z : 0u;
+  s.w = ok ? v.w : 0u;
+  return __builtin_bit_cast(bf16x8, s);
+}
+
+__device__ __forceinline__ float bf2f(bf16 h) { return static_cast<float>(h); }
+__device__ __forceinline__ bf16 f2bf(float f) { return static_cast<bf16>(f); }
+
+__device__ __forceinline__ int kpad(int cin) { return (27 * cin + 31) / 32 * 32; }
+
+// ------------------------------------------------------------------ convolution
+// out[p][co] = sum_k W[co][k] X_k[p] for the D x H x W voxel grid.  The input is
+// either one tensor (CA = 0) or the concatenation of a half-resolution tensor A
+// (CA channels, read at (z>>1, y>>1, x>>1): nearest upsampling) and a
+// full-resolution tensor B (CIN - CA channels).  OUTF = false: out = relu(acc +
+// bias) in BF16; OUTF = true: out = acc in FP32 (backward data pass).
+// One wave computes RB x 16 consecutive voxels for all COUT channels.
+template <int CIN, int COUT, int CA, bool OUTF>
+__global__ __launch_bounds__(kBlock) void k_conv(const bf16* __restrict__ srcA, const bf16* __restrict__ srcB,
+                                                 const bf16* __restrict__ wt, const float* __restrict__ bias,
+                                                 void* __restrict__ out, int D, int H, int W) {
+  constexpr int RB = 4;
+  constexpr int NB = COUT / 16;
+  constexpr int CB = CIN - CA;
+  constexpr int KP = (27 * CIN + 31) / 32 * 32;
+  const long P = (long)D * H * W;
+  const int lane = threadIdx.x & 63;
+  const int g = lane >> 4;
+  const int r16 = lane & 15;
+  const long base = ((long)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)) * (RB * 16);
+  int vz[RB], vy[RB], vx[RB];
+  bool valid[RB];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) {
+    const long p = base + rb * 16 + r16;
+    valid[rb] = p < P;
+    const long q = valid[rb] ? p : 0;
+    vx[rb] = (int)(q % W);
+    vy[rb] = (int)((q / W) % H);
+    vz[rb] = (int)(q / ((long)W * H));
+  }
+  const int H2 = H >> 1, W2 = W >> 1;
+  floatx4 acc[RB][NB];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[rb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const bf16* wrow = wt + (long)r16 * KP + 8 * g;
+  for (int kc = 0; kc < KP; kc += 32) {
+    const int k = kc + 8 * g;
+    const int tap = k / CIN;
+    const int ci = k - tap * CIN;
+    const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+    const bool tap_ok = tap < 27;
+    bf16x8 a[RB];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+      const int z = vz[rb] + dz, y = vy[rb] + dy, x = vx[rb] + dx;
+      const bool ok = valid[rb] && tap_ok && (unsigned)z < (unsigned)D && (unsigned)y < (unsigned)H &&
+                      (unsigned)x < (unsigned)W;
+      const int zc = ok ? z : 0, yc = ok ? y : 0, xc = ok ? x : 0;
+      const bf16* ptr;
+      if (CA > 0 && ci < CA)
+        ptr = srcA + (((long)(zc >> 1) * H2 + (yc >> 1)) * W2 + (xc >> 1)) * CA + ci;
+      else
+        ptr = srcB + (((long)zc * H + yc) * W + xc) * CB + (ci - CA);
+      a[rb] = load8(ptr, ok);
+    }
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const bf16x8 b = *reinterpret_cast<const bf16x8*>(wrow + (long)nb * 16 * KP + kc);
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) acc[rb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rb], b, acc[rb][nb], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const long p = base + rb * 16 + 4 * g + j;
+      if (p >= P) continue;
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const int co = nb * 16 + r16;
+        if (OUTF) {
+          static_cast<float*>(out)[p * COUT + co] = acc[rb][nb][j];
+        } else {
+          const float v = acc[rb][nb][j] + bias[co];
+          static_cast<bf16*>(out)[p * COUT + co] = f2bf(v > 0.f ? v : 0.f);
+        }
+      }
+    }
+}
+
+// --------------------------------------------------------------- weight gradient
+// part[blk][tap][co][CIN] = sum over the block's voxels p of dy[p][co] X_tap[p][ci],
+// X_tap[p] = input at p + offset(tap) (zero outside), sources as in k_conv.
+// Grid (nblk, 27).  Each wave reduces over 32-voxel slices (MFMA k = voxel), the
+// four waves of a block are summed in LDS; the host sums the blocks in order.
+template <int CIN, int COUT, int CA>
+__global__ __launch_bounds__(kBlock) void k_wgrad(const bf16* __restrict__ srcA, const bf16* __restrict__ srcB,
+                                                  const bf16* __restrict__ dy, float* __restrict__ part, int D, int H,
+                                                  int W, long vox_per_block) {
+  constexpr int MB = COUT / 16;
+  constexpr int NC = (CIN + 15) / 16;
+  constexpr int CB = CIN - CA;
+  __shared__ float red[4][MB * NC * 256];
+  const long P = (long)D * H * W;
+  const int tap = blockIdx.y;
+  const int dz = tap / 9 - 1, ddy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int g = lane >> 4;
+  const int r16 = lane & 15;
+  const int H2 = H >> 1, W2 = W >> 1;
+  const long p_begin = (long)blockIdx.x * vox_per_block;
+  const long p_end = p_begin + vox_per_block < P ? p_begin + vox_per_block : P;
+  floatx4 acc[MB][NC];
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int nc = 0; nc < NC; ++nc) acc[mb][nc] = floatx4{0.f, 0.f, 0.f, 0.f};
+  for (long p0 = p_begin + 32 * wave; p0 < p_end; p0 += 128) {
+    bf16x8 a[MB], b[NC];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const long p = p0 + 8 * g + j;
+      const bool vin = p < p_end;
+      const long q = vin ? p : p_begin;
+      const int x = (int)(q % W), y = (int)((q / W) % H), z = (int)(q / ((long)W * H));
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) {
+        const bf16 v = dy[q * COUT + mb * 16 + r16];
+        a[mb][j] = vin ? v : f2bf(0.f);
+      }
+      const int zz = z + dz, yy = y + ddy, xx = x + dx;
+      const bool ok = vin && (unsigned)zz < (unsigned)D && (unsigned)yy < (unsigned)H && (unsigned)xx < (unsigned)W;
+      const int zc = ok ? zz : 0, yc = ok ? yy : 0, xc = ok ? xx : 0;
+#pragma unroll
+      for (int nc = 0; nc < NC; ++nc) {
+        const int ci = nc * 16 + r16;
+        const bool cok = ok && ci < CIN;
+        const int cc = ci < CIN ? ci : 0;
+        const bf16* ptr;
+        if (CA > 0 && cc < CA)
+          ptr = srcA + (((long)(zc >> 1) * H2 + (yc >> 1)) * W2 + (xc >> 1)) * CA + cc;
+        else
+          ptr = srcB + (((long)zc * H + yc) * W + xc) * CB + (cc - CA);
+        const bf16 v = *ptr;
+        b[nc][j] = cok ? v : f2bf(0.f);
+      }
+    }
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int nc = 0; nc < NC; ++nc) acc[mb][nc] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mb], b[nc], acc[mb][nc], 0, 0, 0);
+  }
+  // result tile (mb, nc): lane holds rows co = mb*16 + 4g + j, column ci = nc*16 + r16
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int nc = 0; nc < NC; ++nc)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) red[wave][(mb * NC + nc) * 256 + (4 * g + j) * 16 + r16] = acc[mb][nc][j];
+  __syncthreads();
+  float* dst = part + ((long)blockIdx.x * 27 + tap) * COUT * CIN;
+  for (int e = threadIdx.x; e < MB * NC * 256; e += kBlock) {
+    const int tile = e >> 8, within = e & 255;
+    const int mb = tile / NC, nc = tile % NC;
+    const int co = mb * 16 + (within >> 4), ci = nc * 16 + (within & 15);
+    if (ci < CIN) dst[co * CIN + ci] = red[0][e] + red[1][e] + red[2][e] + red[3][e];
+  }
+}
+
+// grad[(co*27 + tap)*cin_real + ci] = sum_b part[b][tap][co][ci] (fixed order)
+__global__ void k_wgrad_reduce(const float* __restrict__ part, float* __restrict__ grad, int nblk, int cout, int cin,
+                               int cin_real) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= cout * 27 * cin_real) return;
+  const int ci = e % cin_real;
+  const int tap = (e / cin_real) % 27;
+  const int co = e / (cin_real * 27);
+  float s = 0.f;
+  for (int b = 0; b < nblk; ++b) s += part[(((long)b * 27 + tap) * cout + co) * cin + ci];
+  grad[e] = s;
+}
+
+// per-block channel sums of a [P][C] BF16 tensor (C divides 256)
+__global__ __launch_bounds__(kBlock) void k_colsum(const bf16* __restrict__ x, float* __restrict__ part, long P, int C,
+                                                   long vox_per_block) {
+  __shared__ float sm[kBlock];
+  const long e0 = (long)blockIdx.x * vox_per_block * C;
+  long e1 = e0 + vox_per_block * C;
+  if (e1 > P * C) e1 = P * C;
+  float s = 0.f;
+  for (long e = e0 + threadIdx.x; e < e1; e += kBlock) s += bf2f(x[e]);
+  sm[threadIdx.x] = s;
+  __syncthreads();
+  if ((int)threadIdx.x < C) {
+    float t = 0.f;
+    for (int q = threadIdx.x; q < kBlock; q += C) t += sm[q];
+    part[(long)blockIdx.x * C + threadIdx.x] = t;
+  }
+}
+
+// dst[c] = sum_b part[b][c]
+__global__ void k_part_reduce(const float* __restrict__ part, float* __restrict__ dst, int nblk, int C) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= C) return;
+  float s = 0.f;
+  for (int b = 0; b < nblk; ++b) s += part[(long)b * C + c];
+  dst[c] = s;
+}
+
+// ------------------------------------------------------------ pooling, skips
+__global__ void k_pool(const bf16* __restrict__ x, bf16* __restrict__ y, int D, int H, int W, int C) {
+  // y [D/2][H/2][W/2][C] = 2x2x2 mean of x [D][H][W][C]
+  const long n = (long)(D / 2) * (H / 2) * (W / 2) * C;
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const int c = (int)(e % C);
+  const long q = e / C;
+  const int W2 = W / 2, H2 = H / 2;
+  const int x2 = (int)(q % W2), y2 = (int)((q / W2) % H2), z2 = (int)(q / ((long)W2 * H2));
+  float s = 0.f;
+#pragma unroll
+  for (int o = 0; o < 8; ++o) {
+    const int z = 2 * z2 + (o >> 2), yy = 2 * y2 + ((o >> 1) & 1), xx = 2 * x2 + (o & 1);
+    s += bf2f(x[(((long)z * H + yy) * W + xx) * C + c]);
+  }
+  y[e] = f2bf(0.125f * s);
+}
+
+// dd[q][c] = (sum of dc[child][c] over the 8 children of half-res voxel q) * (act[q][c] > 0),
+// c < CA; dc is [D][H][W][CT] FP32 (full resolution), dd and act [D/2][H/2][W/2][CA].
+__global__ void k_upback_mask(const float* __restrict__ dc, const bf16* __restrict__ act, bf16* __restrict__ dd, int D,
+                              int H, int W, int CT, int CA) {
+  const long n = (long)(D / 2) * (H / 2) * (W / 2) * CA;
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const int c = (int)(e % CA);
+  const long q = e / CA;
+  const int W2 = W / 2, H2 = H / 2;
+  const int x2 = (int)(q % W2), y2 = (int)((q / W2) % H2), z2 = (int)(q / ((long)W2 * H2));
+  float s = 0.f;
+#pragma unroll
+  for (int o = 0; o < 8; ++o) {
+    const int z = 2 * z2 + (o >> 2), yy = 2 * y2 + ((o >> 1) & 1), xx = 2 * x2 + (o & 1);
+    s += dc[(((long)z * H + yy) * W + xx) * CT + c];
+  }
+  dd[e] = f2bf(bf2f(act[e]) > 0.f ? s : 0.f);
+}
+
+// de[p][c] = (dc[p][CA + c] + dp[parent(p)][c] / 8) * (act[p][c] > 0): the skip branch
+// plus the backward of the average pooling, masked by the encoder activation.
+__global__ void k_skip_mask(const float* __restrict__ dc, const float* __restrict__ dp, const bf16* __restrict__ act,
+                            bf16* __restrict__ de, int D, int H, int W, int CT, int CA, int CB) {
+  const long n = (long)D * H * W * CB;
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const int c = (int)(e % CB);
+  const long p = e / CB;
+  const int x = (int)(p % W), y = (int)((p / W) % H), z = (int)(p / ((long)W * H));
+  const long par = (((long)(z >> 1) * (H >> 1) + (y >> 1)) * (W >> 1) + (x >> 1)) * CB + c;
+  const float s = dc[p * CT + CA + c] + 0.125f * dp[par];
+  de[e] = f2bf(bf2f(act[e]) > 0.f ? s : 0.f);
+}
+
+// ------------------------------------------------------------------ head, loss
+// y[p] = b + sum_c w[c] d1[p][c]   (16 channels)
+__global__ void k_head_fwd(const bf16* __restrict__ d1, const float* __restrict__ wb, float* __restrict__ y, long P) {
+  const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  const u32x4* src = reinterpret_cast<const u32x4*>(d1 + p * 16);
+  const bf16x8 a = __builtin_bit_cast(bf16x8, src[0]);
+  const bf16x8 b = __builtin_bit_cast(bf16x8, src[1]);
+  float s = wb[16];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) s += wb[c] * bf2f(a[c]) + wb[8 + c] * bf2f(b[c]);
+  y[p] = s;
+}
+
+// dy[p] = 2 (y - t) / P; per-block partial sums of (y - t)^2
+__global__ __launch_bounds__(kBlock) void k_loss(const float* __restrict__ y, const float* __restrict__ t,
+                                                 float* __restrict__ dy, double* __restrict__ part, long P) {
+  __shared__ double sm[kBlock];
+  double s = 0.0;
+  for (long p = (long)blockIdx.x * kBlock + threadIdx.x; p < P; p += (long)gridDim.x * kBlock) {
+    const float d = y[p] - t[p];
+    dy[p] = 2.f * d / (float)P;
+    s += (double)d * d;
+  }
+  sm[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = kBlock / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sm[threadIdx.x] += sm[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sm[0];
+}
+
+// dd1[p][c] = dy[p] w[c] (d1[p][c] > 0); per-block partials of dy*d1 (16) and dy (1)
+__global__ __launch_bounds__(kBlock) void k_head_bwd(const bf16* __restrict__ d1, const float* __restrict__ wb,
+                                                     const float* __restrict__ dy, bf16* __restrict__ dd1,
+                                                     float* __restrict__ part, long P) {
+  __shared__ float sm[17][kBlock];
+  float s[17];
+#pragma unroll
+  for (int c = 0; c < 17; ++c) s[c] = 0.f;
+  for (long p = (long)blockIdx.x * kBlock + threadIdx.x; p < P; p += (long)gridDim.x * kBlock) {
+    const float g = dy[p];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      const float a = bf2f(d1[p * 16 + c]);
+      s[c] += g * a;
+      dd1[p * 16 + c] = f2bf(a > 0.f ? g * wb[c] : 0.f);
+    }
+    s[16] += g;
+  }
+#pragma unroll
+  for (int c = 0; c < 17; ++c) sm[c][threadIdx.x] = s[c];
+  __syncthreads();
+  if ((int)threadIdx.x < 17) {
+    float t = 0.f;
+    for (int q = 0; q < kBlock; ++q) t += sm[threadIdx.x][q];
+    part[(long)blockIdx.x * 17 + threadIdx.x] = t;
+  }
+}
+
+// -------------------------------------------------------------------- Adam
+__global__ void k_adam(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, long n, float lr, float b1, float b2, float eps, float bc1, float bc2) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  w[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+}
+
+// BF16 GEMM weights of a 3x3x3 layer from its FP32 master W[co][27][cin_real]:
+// forward [cout][KP] with k = tap*cinp + ci; transposed-flipped for the backward
+// data pass [cin][KPt] with k = tap*cout + co holding W[co][26 - tap][ci].
+__global__ void k_prep_fwd(const float* __restrict__ w, bf16* __restrict__ out, int cout, int cinp, int cin_real) {
+  const int KP = kpad(cinp);
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)cout * KP) return;
+  const int k = (int)(e % KP), co = (int)(e / KP);
+  const int tap = k / cinp, ci = k % cinp;
+  out[e] = f2bf(tap < 27 && ci < cin_real ? w[((long)co * 27 + tap) * cin_real + ci] : 0.f);
+}
+
+__global__ void k_prep_bwd(const float* __restrict__ w, bf16* __restrict__ out, int cout, int cin) {
+  const int KP = kpad(cout);
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)cin * KP) return;
+  const int k = (int)(e % KP), ci = (int)(e / KP);
+  const int tap = k / cout, co = k % cout;
+  out[e] = f2bf(tap < 27 ? w[((long)co * 27 + (26 - tap)) * cin + ci] : 0.f);
+}
+
+// ------------------------------------------------------- fields <-> network
+__device__ __forceinline__ double cell_vol(const GridDev& g, int i, int j, int k) {
+  return g.x.d[i] * g.y.d[j] * g.z.d[k];
+}
+
+// per-block partials of sum V |w at centre|^2 and sum V r^2
+__global__ __launch_bounds__(kBlock) void k_feat_sums(GridDev g, const double* __restrict__ w,
+                                                      const double* __restrict__ r, double* __restrict__ part) {
+  __shared__ double sa[kBlock], sb[kBlock];
+  const int nx = g.x.n, ny = g.y.n, nz = g.z.n;
+  const long n = (long)nx * ny * nz;
+  const double* u = w;
+  const double* v = w + (long)(nx + 1) * ny * nz;
+  const double* ww = v + (long)nx * (ny + 1) * nz;
+  double a = 0.0, b = 0.0;
+  for (long e = (long)blockIdx.x * kBlock + threadIdx.x; e < n; e += (long)gridDim.x * kBlock) {
+    const int i = (int)(e % nx), j = (int)((e / nx) % ny), k = (int)(e / ((long)nx * ny));
+    const double cx = 0.5 * (u[((long)k * ny + j) * (nx + 1) + i] + u[((long)k * ny + j) * (nx + 1) + i + 1]);
+    const double cy = 0.5 * (v[((long)k * (ny + 1) + j) * nx + i] + v[((long)k * (ny + 1) + j + 1) * nx + i]);
+    const double cz = 0.5 * (ww[((long)k * ny + j) * nx + i] + ww[((long)(k + 1) * ny + j) * nx + i]);
+    const double V = cell_vol(g, i, j, k);
+    a += V * (cx * cx + cy * cy + cz * cz);
+    b += V * r[e] * r[e];
+  }
+  sa[threadIdx.x] = a;
+  sb[threadIdx.x] = b;
+  __syncthreads();
+  for (int o = kBlock / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      sa[threadIdx.x] += sa[threadIdx.x + o];
+      sb[threadIdx.x] += sb[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = sa[0];
+    part[2 * blockIdx.x + 1] = sb[0];
+  }
+}
+
+// x[Dp][Hp][Wp][8] = (w_x, w_y, w_z) / sw, r / sr, 0, 0, 0, 0 on cells; zeros in the padding
+__global__ void k_feat_pack(GridDev g, const double* __restrict__ w, const double* __restrict__ r, bf16* __restrict__ x,
+                            int Dp, int Hp, int Wp, double isw, double isr) {
+  const int nx = g.x.n, ny = g.y.n, nz = g.z.n;
+  const long P = (long)Dp * Hp * Wp;
+  const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  const int i = (int)(p % Wp), j = (int)((p / Wp) % Hp), k = (int)(p / ((long)Wp * Hp));
+  bf16x8 o;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) o[c] = f2bf(0.f);
+  if (i < nx && j < ny && k < nz) {
+    const double* u = w;
+    const double* v = w + (long)(nx + 1) * ny * nz;
+    const double* ww = v + (long)nx * (ny + 1) * nz;
+    const double cx = 0.5 * (u[((long)k * ny + j) * (nx + 1) + i] + u[((long)k * ny + j) * (nx + 1) + i + 1]);
+    const double cy = 0.5 * (v[((long)k * (ny + 1) + j) * nx + i] + v[((long)k * (ny + 1) + j + 1) * nx + i]);
+    const double cz = 0.5 * (ww[((long)k * ny + j) * nx + i] + ww[((long)(k + 1) * ny + j) * nx + i]);
+    o[0] = f2bf((float)(cx * isw));
+    o[1] = f2bf((float)(cy * isw));
+    o[2] = f2bf((float)(cz * isw));
+    o[3] = f2bf((float)(r[((long)k * ny + j) * nx + i] * isr));
+  }
+  *reinterpret_cast<u32x4*>(x + p * 8) = __builtin_bit_cast(u32x4, o);
+}
+
+// x8[p][0..7] = (x4[p][0..3], 0, 0, 0, 0) in BF16
+__global__ void k_x4_to_x8(const float* __restrict__ x4, bf16* __restrict__ x8, long P) {
+  const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  bf16x8 o;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) o[c] = f2bf(c < 4 ? x4[p * 4 + c] : 0.f);
+  *reinterpret_cast<u32x4*>(x8 + p * 8) = __builtin_bit_cast(u32x4, o);
+}
+
+// physical cells of the network output, times s: phi[k][j][i] = s y[k][j][i]
+__global__ void k_unpack(const float* __restrict__ y, double* __restrict__ phi, int nx, int ny, int nz, int Hp, int Wp,
+                         double s) {
+  const long n = (long)nx * ny * nz;
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const int i = (int)(e % nx), j = (int)((e / nx) % ny), k = (int)(e / ((long)nx * ny));
+  phi[e] = s * (double)y[((long)k * Hp + j) * Wp + i];
+}
+
+// training target t = phi * s on cells, 0 in the padding
+__global__ void k_target(const double* __restrict__ phi, float* __restrict__ t, int nx, int ny, int nz, int Dp, int Hp,
+                         int Wp, double s) {
+  const long P = (long)Dp * Hp * Wp;
+  const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  const int i = (int)(p % Wp), j = (int)((p / Wp) % Hp), k = (int)(p / ((long)Wp * Hp));
+  t[p] = (i < nx && j < ny && k < nz) ? (float)(s * phi[((long)k * ny + j) * nx + i]) : 0.f;
+}
+
+// per-block partials of sum V a^2, sum V a b, sum V b^2 over cells
+__global__ __launch_bounds__(kBlock) void k_vdot3(GridDev g, const double* __restrict__ a,
+                                                  const double* __restrict__ b, double* __restrict__ part) {
+  __shared__ double s[3][kBlock];
+  const int nx = g.x.n, ny = g.y.n, nz = g.z.n;
+  const long n = (long)nx * ny * nz;
+  double aa = 0.0, ab = 0.0, bb = 0.0;
+  for (long e = (long)blockIdx.x * kBlock + threadIdx.x; e < n; e += (long)gridDim.x * kBlock) {
+    const int i = (int)(e % nx), j = (int)((e / nx) % ny), k = (int)(e / ((long)nx * ny));
+    const double V = cell_vol(g, i, j, k);
+    aa += V * a[e] * a[e];
+    ab += V * a[e] * b[e];
+    bb += V * b[e] * b[e];
+  }
+  s[0][threadIdx.x] = aa;
+  s[1][threadIdx.x] = ab;
+  s[2][threadIdx.x] = bb;
+  __syncthreads();
+  for (int o = kBlock / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o)
+      for (int q = 0; q < 3; ++q) s[q][threadIdx.x] += s[q][threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int q = 0; q < 3; ++q) part[3 * blockIdx.x + q] = s[q][0];
+}
+
+unsigned blocks(long n, int b = kBlock) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+hipError_t nn_conv(int layer, bool backward, const bf16* a, const bf16* b, const bf16* wt, const float* bias, void* out,
+                   int D, int H, int W, hipStream_t st) {
+  const long P = (long)D * H * W;
+  const dim3 grid(blocks(P, 256)), blk(kBlock);  // 4 waves x 64 voxels
+#define CONV(CIN, COUT, CA, OUTF) \
+  hipLaunchKernelGGL((k_conv<CIN, COUT, CA, OUTF>), grid, blk, 0, st, a, b, wt, bias, out, D, H, W)
+  if (!backward) {
+    switch (layer) {
+      case 0: CONV(8, 16, 0, false); break;
+      case 1: CONV(16, 32, 0, false); break;
+      case 2: CONV(32, 64, 0, false); break;
+      case 3: CONV(96, 32, 64, false); break;
+      case 4: CONV(48, 16, 32, false); break;
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    switch (layer) {
+      case 1: CONV(32, 16, 0, true); break;
+      case 2: CONV(64, 32, 0, true); break;
+      case 3: CONV(32, 96, 0, true); break;
+      case 4: CONV(16, 48, 0, true); break;
+      default: return hipErrorInvalidValue;
+    }
+  }
+#undef CONV
+  return hipGetLastError();
+}
+
+hipError_t nn_wgrad(int layer, const bf16* a, const bf16* b, const bf16* dy, float* part, int nblk, int D, int H, int W,
+                    hipStream_t st) {
+  const long P = (long)D * H * W;
+  const long vpb = ((P + nblk - 1) / nblk + 31) / 32 * 32;
+  const dim3 grid(nblk, 27), blk(kBlock);
+#define WG(CIN, COUT, CA) hipLaunchKernelGGL((k_wgrad<CIN, COUT, CA>), grid, blk, 0, st, a, b, dy, part, D, H, W, vpb)
+  switch (layer) {
+    case 0: WG(8, 16, 0); break;
+    case 1: WG(16, 32, 0); break;
+    case 2: WG(32, 64, 0); break;
+    case 3: WG(96, 32, 64); break;
+    case 4: WG(48, 16, 32); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef WG
+  return hipGetLastError();
+}
+
+hipError_t nn_wgrad_reduce(const float* part, float* grad, int nblk, int cout, int cin, int cin_real, hipStream_t st) {
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks((long)cout * 27 * cin_real)), dim3(kBlock), 0, st, part, grad, nblk,
+                     cout, cin, cin_real);
+  return hipGetLastError();
+}
+
+hipError_t nn_colsum(const bf16* x, float* part, float* dst, long P, int C, int nblk, hipStream_t st) {
+  const long vpb = (P + nblk - 1) / nblk;
+  hipLaunchKernelGGL(k_colsum, dim3(nblk), dim3(kBlock), 0, st, x, part, P, C, vpb);
+  hipLaunchKernelGGL(k_part_reduce, dim3(1), dim3(64), 0, st, part, dst, nblk, C);
+  return hipGetLastError();
+}
+
+hipError_t nn_pool(const bf16* x, bf16* y, int D, int H, int W, int C, hipStream_t st) {
+  hipLaunchKernelGGL(k_pool, dim3(blocks((long)(D / 2) * (H / 2) * (W / 2) * C)), dim3(kBlock), 0, st, x, y, D, H, W, C);
+  return hipGetLastError();
+}
+
+hipError_t nn_upback_mask(const float* dc, const bf16* act, bf16* dd, int D, int H, int W, int CT, int CA,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(k_upback_mask, dim3(blocks((long)(D / 2) * (H / 2) * (W / 2) * CA)), dim3(kBlock), 0, st, dc, act,
+                     dd, D, H, W, CT, CA);
+  return hipGetLastError();
+}
+
+hipError_t nn_skip_mask(const float* dc, const float* dp, const bf16* act, bf16* de, int D, int H, int W, int CT, int CA,
+                        int CB, hipStream_t st) {
+  hipLaunchKernelGGL(k_skip_mask, dim3(blocks((long)D * H * W * CB)), dim3(kBlock), 0, st, dc, dp, act, de, D, H, W, CT,
+                     CA, CB);
+  return hipGetLastError();
+}
+
+hipError_t nn_head_fwd(const bf16* d1, const float* wb, float* y, long P, hipStream_t st) {
+  hipLaunchKernelGGL(k_head_fwd, dim3(blocks(P)), dim3(kBlock), 0, st, d1, wb, y, P);
+  return hipGetLastError();
+}
+
+hipError_t nn_loss(const float* y, const float* t, float* dy, double* part, int nblk, long P, hipStream_t st) {
+  hipLaunchKernelGGL(k_loss, dim3(nblk), dim3(kBlock), 0, st, y, t, dy, part, P);
+  return hipGetLastError();
+}
+
+hipError_t nn_head_bwd(const bf16* d1, const float* wb, const float* dy, bf16* dd1, float* part, float* gdst, int nblk,
+                       long P, hipStream_t st) {
+  hipLaunchKernelGGL(k_head_bwd, dim3(nblk), dim3(kBlock), 0, st, d1, wb, dy, dd1, part, P);
+  hipLaunchKernelGGL(k_part_reduce, dim3(1), dim3(64), 0, st, part, gdst, nblk, 17);
+  return hipGetLastError();
+}
+
+hipError_t nn_adam(float* w, const float* g, float* m, float* v, long n, float lr, float b1, float b2, float eps,
+                   float bc1, float bc2, hipStream_t st) {
+  hipLaunchKernelGGL(k_adam, dim3(blocks(n)), dim3(kBlock), 0, st, w, g, m, v, n, lr, b1, b2, eps, bc1, bc2);
+  return hipGetLastError();
+}
+
+hipError_t nn_prep(const float* w, bf16* fwd, bf16* bwd, int cout, int cinp, int cin_real, hipStream_t st) {
+  const int KP = (27 * cinp + 31) / 32 * 32;
+  hipLaunchKernelGGL(k_prep_fwd, dim3(blocks((long)cout * KP)), dim3(kBlock), 0, st, w, fwd, cout, cinp, cin_real);
+  if (bwd) {
+    const int KPt = (27 * cout + 31) / 32 * 32;
+    hipLaunchKernelGGL(k_prep_bwd, dim3(blocks((long)cin_real * KPt)), dim3(kBlock), 0, st, w, bwd, cout, cin_real);
+  }
+  return hipGetLastError();
+}
+
+hipError_t nn_feat_sums(const GridDev& g, const double* w, const double* r, double* part, int nblk, hipStream_t st) {
+  hipLaunchKernelGGL(k_feat_sums, dim3(nblk), dim3(kBlock), 0, st, g, w, r, part);
+  return hipGetLastError();
+}
+
+hipError_t nn_feat_pack(const GridDev& g, const double* w, const double* r, bf16* x, int Dp, int Hp, int Wp, double isw,
+                        double isr, hipStream_t st) {
+  hipLaunchKernelGGL(k_feat_pack, dim3(blocks((long)Dp * Hp * Wp)), dim3(kBlock), 0, st, g, w, r, x, Dp, Hp, Wp, isw,
+                     isr);
+  return hipGetLastError();
+}
+
+hipError_t nn_x4_to_x8(const float* x4, bf16* x8, long P, hipStream_t st) {
+  hipLaunchKernelGGL(k_x4_to_x8, dim3(blocks(P)), dim3(kBlock), 0, st, x4, x8, P);
+  return hipGetLastError();
+}
+
+hipError_t nn_unpack(const float* y, double* phi, int nx, int ny, int nz, int Hp, int Wp, double s, hipStream_t st) {
+  hipLaunchKernelGGL(k_unpack, dim3(blocks((long)nx * ny * nz)), dim3(kBlock), 0, st, y, phi, nx, ny, nz, Hp, Wp, s);
+  return hipGetLastError();
+}
+
+hipError_t nn_target(const double* phi, float* t, int nx, int ny, int nz, int Dp, int Hp, int Wp, double s,
+                     hipStream_t st) {
+  hipLaunchKernelGGL(k_target, dim3(blocks((long)Dp * Hp * Wp)), dim3(kBlock), 0, st, phi, t, nx, ny, nz, Dp, Hp, Wp, s);
+  return hipGetLastError();
+}
+
+hipError_t nn_vdot3(const GridDev& g, const double* a, const double* b, double* part, int nblk, hipStream_t st) {
+  hipLaunchKernelGGL(k_vdot3, dim3(nblk), dim3(kBlock), 0, st, g, a, b, part);
+  return hipGetLastError();
+}
+
+}  // namespace lk

@@ -1,0 +1,242 @@
+"""GPU parity of the learned pressure-correction guess against the FP64 oracle.
+
+The network keeps weights, activations and inter-layer gradients in BF16 and
+accumulates in FP32 (the head's weights stay FP32).  Two comparisons:
+
+* against the oracle run with the same BF16 roundings at the same storage points
+  (oracle.nn's q hook, weights and input rounded the same way): what remains is
+  the FP32 summation order, which flips an occasional BF16 rounding, so the
+  bound is tight (1e-3 of the norm forward, 1e-2 for gradients, whose sums over
+  voxels cancel);
+* against the exact FP64 network: the BF16 storage itself, unit roundoff 2^-9
+  per rounding, compounded along the backward chain and amplified by the
+  cancellation in the weight-gradient sums (loose: 1e-2 forward, 0.1 gradients).
+"""
+import numpy as np
+import pytest
+
+from oracle import nn
+from oracle.grid import Grid
+from oracle import simple
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def rounded(p):
+    """Parameters as the GPU network uses them: BF16 conv weights, FP32 head and biases."""
+    pr = {k: (nn.bf16(v) if k.endswith(".w") and not k.startswith("head") else v) for k, v in p.items()}
+    return pr
+
+
+def flat(p):
+    return np.concatenate([np.concatenate([p[n + ".w"].ravel(), p[n + ".b"].ravel()]) for n, *_ in nn.LAYERS])
+
+
+def unflat(v):
+    out, o = {}, 0
+    for name, ci, co, k in nn.LAYERS:
+        taps = 27 if k == 3 else 1
+        out[name + ".w"] = v[o:o + co * taps * ci].reshape(co, taps, ci)
+        o += co * taps * ci
+        out[name + ".b"] = v[o:o + co]
+        o += co
+    return out
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def lk():
+    import paper_1704_08521_amd as lk
+    return lk
+
+
+def make_params(seed):
+    p = nn.init_params(seed)
+    rng = np.random.default_rng(seed + 100)
+    for k in p:
+        if k.endswith(".b"):
+            p[k] = 0.05 * rng.standard_normal(p[k].shape)
+    return p
+
+
+@pytest.mark.parametrize("shape", [(8, 12, 16), (4, 8, 4), (12, 4, 8)])
+def test_forward_matches_oracle(lk, shape):
+    import torch
+    D, H, W = shape
+    p = make_params(1)
+    net = lk.Net()
+    net.set_params(flat(p))
+    x = np.random.default_rng(2).standard_normal((D, H, W, 4))
+    y = net.forward(torch.from_numpy(x.astype(np.float32)).cuda()).cpu().numpy()
+    ye = nn.forward(rounded(p), nn.bf16(x), q=nn.bf16)[0][..., 0]
+    yo = nn.forward(p, x)[0][..., 0]
+    e, e64 = rel(y, ye), rel(y, yo)
+    print(f"forward {shape}: rel err {e:.2e} (same roundings), {e64:.2e} (exact FP64)")
+    assert e < 1e-3
+    assert e64 < 1e-2
+
+
+def test_gradients_match_oracle(lk):
+    import torch
+    D, H, W = 8, 8, 8
+    p = make_params(3)
+    net = lk.Net()
+    net.set_params(flat(p))
+    rng = np.random.default_rng(4)
+    x = rng.standard_normal((D, H, W, 4))
+    t = rng.standard_normal((D, H, W))
+    loss, g = net.step(torch.from_numpy(x.astype(np.float32)).cuda(),
+                       torch.from_numpy(t.astype(np.float32)).cuda(), lr=0.0, grads=True)
+    le, ge = nn.loss_and_grad(rounded(p), nn.bf16(x), t[..., None], q=nn.bf16)
+    lo, go = nn.loss_and_grad(p, x, t[..., None])
+    assert abs(loss - le) <= 1e-4 * le
+    assert abs(loss - lo) <= 1e-2 * lo
+    gg = unflat(g.astype(np.float64))
+    for name, *_ in nn.LAYERS:
+        for suf in (".w", ".b"):
+            e, e64 = rel(gg[name + suf], ge[name + suf]), rel(gg[name + suf], go[name + suf])
+            print(f"grad {name}{suf}: rel err {e:.2e} (same roundings), {e64:.2e} (exact FP64)")
+            assert e < 1e-2, (name + suf, e)
+            assert e64 < 0.1, (name + suf, e64)
+
+
+def test_adam_step_matches_oracle(lk):
+    import torch
+    D, H, W = 8, 8, 4
+    p = make_params(5)
+    net = lk.Net()
+    net.set_params(flat(p))
+    rng = np.random.default_rng(6)
+    x = torch.from_numpy(rng.standard_normal((D, H, W, 4)).astype(np.float32)).cuda()
+    t = torch.from_numpy(rng.standard_normal((D, H, W)).astype(np.float32)).cuda()
+    w0 = net.get_params().astype(np.float64)
+    _, g = net.step(x, t, lr=1e-3, grads=True)
+    w1 = net.get_params().astype(np.float64)
+    # the oracle's Adam on the gradients the GPU computed
+    po, go = unflat(w0.copy()), unflat(g.astype(np.float64))
+    m = {k: np.zeros_like(v) for k, v in po.items()}
+    v = {k: np.zeros_like(v) for k, v in po.items()}
+    nn.adam(po, go, m, v, 1, lr=1e-3)
+    assert np.allclose(w1, flat(po), rtol=0, atol=1e-6)
+
+
+# ------------------------------------------------------------------ inside SIMPLE
+def setup_ctx(lk, n, kind, re, seed=1000):
+    import torch
+    ctx = lk.Context(*n)
+    ctx.set_stretching(kind, 10.0 if kind == "tanh" else 0.0)
+    ctx.set_re(re)
+    ctx.set_lid(0.0)
+    r = torch.from_numpy(synth.random_velocity(*n, seed)).cuda()
+    U, _, _ = ctx.project(r, tol=1e-12, max_iter=4)
+    U /= U.abs().max()
+    ctx.set_base_flow(U)
+    return ctx, U.cpu().numpy()
+
+
+def oracle_grid(n, kind):
+    return Grid.make(*n, kind=kind, ratio=10.0)
+
+
+def krylov_input(ctx, seed):
+    import torch
+    r = torch.from_numpy(synth.random_velocity(ctx.nx, ctx.ny, ctx.nz, seed)).cuda()
+    v, _, _ = ctx.project(r, tol=1e-12, max_iter=4)
+    return v / torch.linalg.vector_norm(v)
+
+
+def test_fallback_keeps_plain_result(lk):
+    """A network whose output is constant gives D G y = 0: the loop starts plainly."""
+    n = (12, 10, 8)
+    ctx, U = setup_ctx(lk, n, "sine", 300.0)
+    net = lk.Net()
+    net.set_params(np.zeros(net.nparams, dtype=np.float32))
+    ctx.set_net(net)
+    v = krylov_input(ctx, 5)
+    out, _, st = ctx.krylov_vector(v, precision=lk.LEARNED, tol=1e-10)
+    assert not st["guess_used"] and st["guess_eps"] == 1.0 and st["converged"]
+    g = oracle_grid(n, "sine")
+    ref, _ = simple.Projector(g).krylov_vector(U, v.cpu().numpy(), 300.0)
+    assert rel(out.cpu().numpy(), ref) < 1e-9
+
+
+@pytest.fixture(scope="module")
+def trained(lk):
+    """A network trained on 32^3 tanh-10 pairs at Re = 1000 (the method's own corrections)."""
+    n = (32, 32, 32)
+    ctx, U = setup_ctx(lk, n, "tanh", 1000.0)
+    net = lk.Net(seed=11)
+    untrained = lk.Net(seed=11)
+    hist = net.train(ctx, steps=300, lr=2e-3, seed=7)
+    return ctx, U, net, untrained, hist
+
+
+def test_guess_matches_oracle(lk, trained):
+    """The scaled guess of a trained network on a different (odd, padded) grid
+    against the oracle's guess with the same parameters and roundings."""
+    _, _, net, _, _ = trained
+    n = (13, 10, 9)
+    ctx, _ = setup_ctx(lk, n, "tanh", 500.0)
+    ctx.set_net(net)
+    v = krylov_input(ctx, 3)
+    w = ctx.jacobian_apply(v)
+    phi0, eps = ctx.learned_guess(w)
+    p = unflat(net.get_params().astype(np.float64))
+    phio, epso = nn.guess(oracle_grid(n, "tanh"), rounded(p), w.cpu().numpy(), q=nn.bf16)
+    e = rel(phi0.cpu().numpy(), phio.ravel())
+    print(f"guess eps gpu {eps:.6f} oracle {epso:.6f}; phi0 rel err {e:.2e}")
+    assert epso < 0.99
+    assert abs(eps - epso) <= 1e-6
+    assert e < 1e-6
+
+
+def test_training_reduces_loss(trained):
+    _, _, _, _, hist = trained
+    first, last = float(np.mean(hist[:10])), float(np.mean(hist[-30:]))
+    print(f"training loss: first 10 {first:.4f}, last 30 {last:.4f}")
+    assert np.all(np.isfinite(hist))
+    assert last < 0.5 * first
+
+
+def test_learned_krylov_vector_equals_plain(lk, trained):
+    ctx, U, net, _, _ = trained
+    ctx.set_net(net)
+    g = oracle_grid((32, 32, 32), "tanh")
+    P = simple.Projector(g)
+    for seed in (501, 502):
+        v = krylov_input(ctx, seed)
+        out, _, st = ctx.krylov_vector(v, precision=lk.LEARNED, tol=1e-10, max_iter=8)
+        assert st["converged"] and st["rho"] <= 1e-10
+        ref, _ = P.krylov_vector(U, v.cpu().numpy(), 1000.0)
+        e = rel(out.cpu().numpy(), ref)
+        print(f"seed {seed}: guess_used {st['guess_used']} eps {st['guess_eps']:.4f} passes {st['iterations']} "
+              f"rel err vs oracle {e:.2e}")
+        assert e < 1e-9
+
+
+def test_trained_network_gain(lk, trained):
+    """What the trained network gains over the method without it: the continuity
+    residual right after the guess (plain start: 1) and after the first mixed pass,
+    on held-out inputs, next to the untrained network."""
+    ctx, _, net, untrained, _ = trained
+    rows = []
+    for seed in range(601, 609):
+        v = krylov_input(ctx, seed)
+        res = {}
+        for name, n_ in (("trained", net), ("untrained", untrained)):
+            ctx.set_net(n_)
+            _, _, st = ctx.krylov_vector(v, precision=lk.LEARNED, tol=1e-10, max_iter=8)
+            res[name] = (st["guess_eps"], st["rho_hist"][0] if st["rho_hist"] else st["rho"], st["iterations"])
+        _, _, stm = ctx.krylov_vector(v, precision=lk.MIXED, tol=1e-10, max_iter=8)
+        rows.append((seed, res["trained"], res["untrained"], (stm["rho_hist"][0], stm["iterations"])))
+    print("\nseed | trained eps, rho1, passes | untrained eps, rho1, passes | mixed rho1, passes")
+    for seed, tr, un, mx in rows:
+        print(f"{seed} | {tr[0]:.4f} {tr[1]:.2e} {tr[2]} | {un[0]:.4f} {un[1]:.2e} {un[2]} | {mx[0]:.2e} {mx[1]}")
+    eps_t = np.mean([r[1][0] for r in rows])
+    eps_u = np.mean([r[2][0] for r in rows])
+    print(f"mean eps after guess: trained {eps_t:.4f}, untrained {eps_u:.4f} (plain start 1)")
+    assert eps_t < 1.0 and eps_t < eps_u

@@ -7,7 +7,8 @@
 
 namespace lk {
 
-__device__ __forceinline__ double lerp(double a0, double a1, double t) { return (1.0 - t) * a0 + t * a1; }
+// a0 + t (a1 - a0): one subtraction and one FMA
+__device__ __forceinline__ double lerp(double a0, double a1, double t) { return fma(t, a1 - a0, a0); }
 
 // Linear offsets of the staggered arrays, x fastest.
 struct Idx {

@@ -18,72 +18,79 @@ namespace {
 // lid velocity at z = 1 (eq. 4).  With these ghosts the wall fluxes of the
 // Laplacian ((first - wall)/half width) and the vanishing edge fluxes on walls
 // follow from the interior formulas, so the compute has no wall branches.
-constexpr int MTX = 64, MTY = 4;
-constexpr int MPX = MTX + 2, MPY = MTY + 2, MPS = MPX * MPY;
 
-// Value of component `comp` at (k, j, i) with the ghost rule above.  Branch
-// free: the load is unconditional from an in-range offset (0 for ghosts) and the
-// ghost is selected afterwards, so a thread's loads all issue back to back.
-template <bool LID>
-__device__ __forceinline__ double tap_load(const double* __restrict__ p, int comp, bool adv, int nx, int ny, int nz,
-                                           int k, int j, int i, double lid_u, double lid_v) {
-  bool ok, tang;
-  long off;
-  double lid;
-  if (comp == 0) {  // u: i in [0, nx] (walls at 0, nx), j < ny, k < nz
-    tang = (i > 0) & (i < nx) & (j >= 0) & (j < ny);
-    ok = tang & (k >= 0) & (k < nz);
-    off = ((long)k * ny + j) * (nx + 1) + i;
-    lid = lid_u;
-  } else if (comp == 1) {  // v: j in [0, ny] (walls), i < nx, k < nz
-    tang = (j > 0) & (j < ny) & (i >= 0) & (i < nx);
-    ok = tang & (k >= 0) & (k < nz);
-    off = ((long)k * (ny + 1) + j) * nx + i;
-    lid = lid_v;
-  } else {  // w: k in [0, nz] (walls), i < nx, j < ny
-    tang = false;
-    ok = (k > 0) & (k < nz) & (i >= 0) & (i < nx) & (j >= 0) & (j < ny);
-    off = ((long)k * ny + j) * nx + i;
-    lid = 0.0;
-  }
-  const double x = p[ok ? off : 0];
-  const double ghost = (LID && !adv && tang && k == nz) ? lid : 0.0;
-  return ok ? x : ghost;
+// Block id -> tile: workgroups are dispatched round-robin over the 8 XCDs, so
+// consecutive ids land on different L2s.  Renumber so that each XCD receives a
+// contiguous range of tiles (x fastest, then y, then z chunk): neighbouring tiles
+// share their halo rows and overlap planes through the same L2.
+__device__ __forceinline__ int xcd_tile(int bid, int nb) {
+  constexpr int NX = 8;
+  const int xcd = bid % NX, local = bid / NX;
+  const int per = nb / NX, rem = nb % NX;
+  return xcd < rem ? xcd * (per + 1) + local : rem * (per + 1) + (xcd - rem) * per + local;
 }
 
-template <bool LID>
-__global__ void __launch_bounds__(MTX* MTY) k_momentum(GridDev g, const double* __restrict__ a,
-                                                      const double* __restrict__ b, double* __restrict__ out,
-                                                      double rre, double s, double lid_u, double lid_v, int kchunk) {
+template <bool LID, int TX, int TY, int PF>
+__global__ void __launch_bounds__(TX* TY) k_momentum(GridDev g, const double* __restrict__ a,
+                                                    const double* __restrict__ b, double* __restrict__ out, double rre,
+                                                    double s, double lid_u, double lid_v, int kchunk, int nbx,
+                                                    int nby) {
+  constexpr int MPX = TX + 2, MPY = TY + 2, MPS = MPX * MPY;
   __shared__ double sm[6][3][MPS];  // 0..2: a (u, v, w); 3..5: b (u, v, w)
   const int nx = g.x.n, ny = g.y.n, nz = g.z.n;
   const size_t nu = (size_t)(nx + 1) * ny * nz, nv = (size_t)nx * (ny + 1) * nz;
-  const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * MTX + tx;
-  const int i0 = blockIdx.x * MTX, j0 = blockIdx.y * MTY;
-  const int kb = blockIdx.z * kchunk;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int bx = tile % nbx, by = (tile / nbx) % nby, bz = tile / (nbx * nby);
+  const int tx = threadIdx.x % TX, ty = threadIdx.x / TX, tid = threadIdx.x;
+  const int i0 = bx * TX, j0 = by * TY;
+  const int kb = bz * kchunk;
   const int ke = min(kb + kchunk, nz + 1);
   const int i = i0 + tx, j = j0 + ty;
   const double* src[6] = {a, a + nu, a + nu + nv, b, b + nu, b + nu + nv};
 
-  // Plane loads go to registers first (all issued back to back from in-range
-  // addresses, ghosts selected afterwards) and are written to LDS one step later,
-  // so the next plane is in flight while the current one is computed.
-  constexpr int NT = MTX * MTY;
+  // Halo positions of this thread (fixed along the march): in-plane offset and
+  // in-range flag per component; a plane adds k * (plane stride).  Loads are
+  // unconditional from an in-range address (0 for ghosts), the ghost is selected
+  // afterwards, so all of a thread's loads issue back to back.
+  constexpr int NT = TX * TY;
   constexpr int PER = (MPS + NT - 1) / NT;
-  double reg[6][PER];
-  auto load = [&](int k) {
+  int col[3][PER];
+  bool xy[3][PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int e = min(tid + q * NT, MPS - 1);  // the surplus threads re-read the last entry
+    const int jj = j0 - 1 + e / MPX, ii = i0 - 1 + e % MPX;
+    const bool in_i = (ii >= 0) & (ii < nx), in_j = (jj >= 0) & (jj < ny);
+    xy[0][q] = (ii > 0) & (ii < nx) & in_j;
+    xy[1][q] = (jj > 0) & (jj < ny) & in_i;
+    xy[2][q] = in_i & in_j;
+    col[0][q] = xy[0][q] ? jj * (nx + 1) + ii : 0;
+    col[1][q] = xy[1][q] ? jj * nx + ii : 0;
+    col[2][q] = xy[2][q] ? jj * nx + ii : 0;
+  }
+  const long pstride[3] = {(long)ny * (nx + 1), (long)(ny + 1) * nx, (long)ny * nx};
+
+  // Plane loads go to registers first and are written to LDS PF steps later, so
+  // the next PF planes are in flight while the current one is computed.
+  double r0[6][PER], r1[6][PER];
+  auto load = [&](double(&reg)[6][PER], int k) {
+    const bool kin_uv = (k >= 0) & (k < nz), kin_w = (k > 0) & (k < nz);
 #pragma unroll
     for (int arr = 0; arr < 6; ++arr) {
+      const int comp = arr % 3;
+      const bool kin = comp == 2 ? kin_w : kin_uv;
+      const long kofs = kin ? (long)k * pstride[comp] : 0;
+      const double lid = comp == 0 ? lid_u : lid_v;
 #pragma unroll
       for (int q = 0; q < PER; ++q) {
-        const int e = min(tid + q * NT, MPS - 1);  // the surplus threads re-read the last entry
-        const int yy = e / MPX, xx = e - yy * MPX;
-        reg[arr][q] = tap_load<LID>(src[arr], arr % 3, arr < 3, nx, ny, nz, k, j0 - 1 + yy, i0 - 1 + xx, lid_u,
-                                    lid_v);
+        const bool ok = kin & xy[comp][q];
+        const double x = src[arr][kofs + col[comp][q]];
+        const double ghost = (LID && arr >= 3 && comp < 2 && xy[comp][q] && k == nz) ? lid : 0.0;
+        reg[arr][q] = ok ? x : ghost;
       }
     }
   };
-  auto store = [&](int k) {
+  auto store = [&](const double(&reg)[6][PER], int k) {
     const int slot = (k + 3) % 3;
 #pragma unroll
     for (int arr = 0; arr < 6; ++arr) {
@@ -103,15 +110,7 @@ __global__ void __launch_bounds__(MTX* MTY) k_momentum(GridDev g, const double* 
   const double rdy0 = (j < ny) ? g.y.rd[j] : 0.0, rdym = (j >= 1 && j - 1 < ny) ? g.y.rd[j - 1] : 0.0;
   const double rddy0 = (j <= ny) ? g.y.rdd[j] : 0.0, rddy1 = (j + 1 <= ny) ? g.y.rdd[j + 1] : 0.0;
 
-  load(kb - 1);
-  store(kb - 1);
-  load(kb);
-  store(kb);
-  load(kb + 1);
-  for (int k = kb; k < ke; ++k) {
-    store(k + 1);
-    __syncthreads();
-    if (k + 2 <= ke) load(k + 2);
+  auto compute = [&](int k) {
     const int pm = (k + 2) % 3, p0 = k % 3, pp = (k + 1) % 3;  // planes k-1, k, k+1
     // S(arr, plane, dj, di)
 #define S(arr, pl, dj, di) sm[arr][pl][(ty + 1 + (dj)) * MPX + (tx + 1 + (di))]
@@ -269,7 +268,37 @@ __global__ void __launch_bounds__(MTX* MTY) k_momentum(GridDev g, const double* 
       out[nu + nv + ((size_t)k * ny + j) * nx + i] = val;
     }
 #undef S
-    __syncthreads();
+  };
+
+  load(r0, kb - 1);
+  store(r0, kb - 1);
+  load(r0, kb);
+  store(r0, kb);
+  load(r0, kb + 1);
+  if (PF == 1) {
+    for (int k = kb; k < ke; ++k) {
+      store(r0, k + 1);
+      __syncthreads();
+      if (k + 2 <= ke) load(r0, k + 2);
+      compute(k);
+      __syncthreads();
+    }
+  } else {
+    // two planes in flight: r0 carries planes kb+1, kb+3, ...; r1 planes kb+2, kb+4, ...
+    if (kb + 2 <= ke) load(r1, kb + 2);
+    for (int k = kb; k < ke; k += 2) {
+      store(r0, k + 1);
+      __syncthreads();
+      if (k + 3 <= ke) load(r0, k + 3);
+      compute(k);
+      __syncthreads();
+      if (k + 1 >= ke) break;
+      store(r1, k + 2);
+      __syncthreads();
+      if (k + 4 <= ke) load(r1, k + 4);
+      compute(k + 1);
+      __syncthreads();
+    }
   }
 }
 
@@ -341,16 +370,21 @@ __global__ void __launch_bounds__(256) k_correct(GridDev g, const double* __rest
 }  // namespace
 
 // ==================================================================== launchers
+// Tile of the momentum stencil: TX x TY threads, kMomChunk planes per block.
+constexpr int kMomTX = 16, kMomTY = 16, kMomChunk = 24, kMomPF = 1;
+
 hipError_t launch_momentum(const GridDev& g, const double* a, const double* b, double* out, double rre, double s,
                            bool lid, double lid_u, double lid_v, hipStream_t st) {
   const int nx = g.x.n, ny = g.y.n, nz = g.z.n;
-  const int kchunk = 24;
-  dim3 block(MTX, MTY, 1);
-  dim3 grid(blocks_for(nx + 1, MTX), blocks_for(ny + 1, MTY), blocks_for(nz + 1, kchunk));
+  const int nbx = (int)blocks_for(nx + 1, kMomTX), nby = (int)blocks_for(ny + 1, kMomTY);
+  const int nbz = (int)blocks_for(nz + 1, kMomChunk);
+  const dim3 grid(nbx * nby * nbz), block(kMomTX * kMomTY);
   if (lid)
-    hipLaunchKernelGGL(k_momentum<true>, grid, block, 0, st, g, a, b, out, rre, s, lid_u, lid_v, kchunk);
+    hipLaunchKernelGGL((k_momentum<true, kMomTX, kMomTY, kMomPF>), grid, block, 0, st, g, a, b, out, rre, s, lid_u, lid_v,
+                       kMomChunk, nbx, nby);
   else
-    hipLaunchKernelGGL(k_momentum<false>, grid, block, 0, st, g, a, b, out, rre, s, 0.0, 0.0, kchunk);
+    hipLaunchKernelGGL((k_momentum<false, kMomTX, kMomTY, kMomPF>), grid, block, 0, st, g, a, b, out, rre, s, 0.0, 0.0,
+                       kMomChunk, nbx, nby);
   return hipGetLastError();
 }
 

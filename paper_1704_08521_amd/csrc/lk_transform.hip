@@ -12,20 +12,18 @@ namespace {
 
 constexpr int TPR = 16;  // thread rows
 constexpr int TPC = 16;  // thread columns
-constexpr int TBK = 16;  // contraction chunk
 
 // Left transform: C[m][n] = sum_k A[m][k] B[k][n]; A is the n_axis x n_axis mode
 // matrix, B the data with "segmented" columns: column n starts at
 // (n / nseg) * seg_stride + n % nseg and consecutive k are kstride apart.  C has
 // B's layout.  With scale set, C[m][n] is divided by lam_m + ly[j] + lx[i]
 // (n = j*nx + i), and the constant mode (m, j, i) = (zm, zj, zi) is zeroed.
-template <typename T, int TM>
+template <typename T, int TM, int TN, int TBK>
 __global__ void __launch_bounds__(TPR* TPC) k_tp_left(int M, int N, int K, const T* __restrict__ A,
                                                       const T* __restrict__ B, T* __restrict__ C, int nseg,
                                                       long seg_stride, long kstride, const double* __restrict__ lm,
                                                       const double* __restrict__ ly, const double* __restrict__ lx,
                                                       int nxs, int zm, int zj, int zi) {
-  constexpr int TN = 4;
   constexpr int BM = TPR * TM, BN = TPC * TN;
   __shared__ T As[TBK][BM + 1];
   __shared__ T Bs[TBK][BN];
@@ -114,10 +112,9 @@ __global__ void __launch_bounds__(TPR* TPC) k_tp_left(int M, int N, int K, const
 
 // Right transform: C[m][n] = sum_k A[m][k] B[k][n]; A is the data (lines of
 // length K, contiguous), B the K x N mode matrix (transposed), C lines of N.
-template <typename T, int TN>
+template <typename T, int TM, int TN, int TBK>
 __global__ void __launch_bounds__(TPR* TPC) k_tp_right(int M, int N, int K, const T* __restrict__ A,
                                                        const T* __restrict__ B, T* __restrict__ C) {
-  constexpr int TM = 4;
   constexpr int BM = TPR * TM, BN = TPC * TN;
   __shared__ T As[TBK][BM + 1];
   __shared__ T Bs[TBK][BN];
@@ -196,8 +193,11 @@ __global__ void __launch_bounds__(TPR* TPC) k_tp_right(int M, int N, int K, cons
   }
 }
 
-// Smallest register tile that covers n with 16 threads (n > 256 uses several blocks).
+// Register tile along the transformed dimension: the smallest that covers n with 16
+// threads, except that 161..224 uses 7 (two blocks of 112), which measured faster at
+// n = 200 than one block of 13 (n > 256 uses several blocks).
 inline int pick_tile(int n) {
+  if (n > 160 && n <= 224) return 7;
   const int need = (n + 15) / 16;
   const int opts[] = {1, 2, 4, 8, 10, 13, 16};
   for (int t : opts)
@@ -210,7 +210,7 @@ hipError_t left_launch(int M, int N, int K, const T* A, const T* B, T* C, int ns
                        const double* lm, const double* ly, const double* lx, int nxs, int zm, int zj, int zi,
                        hipStream_t st) {
   dim3 grid(blocks_for(N, TPC * 4), blocks_for(M, TPR * TM), 1);
-  hipLaunchKernelGGL((k_tp_left<T, TM>), grid, dim3(TPR * TPC), 0, st, M, N, K, A, B, C, nseg, seg_stride, kstride,
+  hipLaunchKernelGGL((k_tp_left<T, TM, 4, 16>), grid, dim3(TPR * TPC), 0, st, M, N, K, A, B, C, nseg, seg_stride, kstride,
                      lm, ly, lx, nxs, zm, zj, zi);
   return hipGetLastError();
 }
@@ -218,7 +218,7 @@ hipError_t left_launch(int M, int N, int K, const T* A, const T* B, T* C, int ns
 template <typename T, int TN>
 hipError_t right_launch(int M, int N, int K, const T* A, const T* B, T* C, hipStream_t st) {
   dim3 grid(blocks_for(N, TPC * TN), blocks_for(M, TPR * 4), 1);
-  hipLaunchKernelGGL((k_tp_right<T, TN>), grid, dim3(TPR * TPC), 0, st, M, N, K, A, B, C);
+  hipLaunchKernelGGL((k_tp_right<T, 4, TN, 16>), grid, dim3(TPR * TPC), 0, st, M, N, K, A, B, C);
   return hipGetLastError();
 }
 
@@ -233,6 +233,7 @@ hipError_t launch_tp_left(int M, int N, int K, const T* A, const T* B, T* C, int
     case 2: return left_launch<T, 2>(M, N, K, A, B, C, nseg, seg_stride, kstride, lm, ly, lx, nxs, zm, zj, zi, st);
     case 4: return left_launch<T, 4>(M, N, K, A, B, C, nseg, seg_stride, kstride, lm, ly, lx, nxs, zm, zj, zi, st);
     case 8: return left_launch<T, 8>(M, N, K, A, B, C, nseg, seg_stride, kstride, lm, ly, lx, nxs, zm, zj, zi, st);
+    case 7: return left_launch<T, 7>(M, N, K, A, B, C, nseg, seg_stride, kstride, lm, ly, lx, nxs, zm, zj, zi, st);
     case 10: return left_launch<T, 10>(M, N, K, A, B, C, nseg, seg_stride, kstride, lm, ly, lx, nxs, zm, zj, zi, st);
     case 13: return left_launch<T, 13>(M, N, K, A, B, C, nseg, seg_stride, kstride, lm, ly, lx, nxs, zm, zj, zi, st);
     default: return left_launch<T, 16>(M, N, K, A, B, C, nseg, seg_stride, kstride, lm, ly, lx, nxs, zm, zj, zi, st);
@@ -246,6 +247,7 @@ hipError_t launch_tp_right(int M, int N, int K, const T* A, const T* B, T* C, hi
     case 2: return right_launch<T, 2>(M, N, K, A, B, C, st);
     case 4: return right_launch<T, 4>(M, N, K, A, B, C, st);
     case 8: return right_launch<T, 8>(M, N, K, A, B, C, st);
+    case 7: return right_launch<T, 7>(M, N, K, A, B, C, st);
     case 10: return right_launch<T, 10>(M, N, K, A, B, C, st);
     case 13: return right_launch<T, 13>(M, N, K, A, B, C, st);
     default: return right_launch<T, 16>(M, N, K, A, B, C, st);

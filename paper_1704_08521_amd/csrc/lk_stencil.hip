@@ -30,7 +30,7 @@ __device__ __forceinline__ int xcd_tile(int bid, int nb) {
   return xcd < rem ? xcd * (per + 1) + local : rem * (per + 1) + (xcd - rem) * per + local;
 }
 
-template <bool LID, int TX, int TY, int PF>
+template <bool LID, int TX, int TY>
 __global__ void __launch_bounds__(TX* TY) k_momentum(GridDev g, const double* __restrict__ a,
                                                     const double* __restrict__ b, double* __restrict__ out, double rre,
                                                     double s, double lid_u, double lid_v, int kchunk, int nbx,
@@ -70,9 +70,9 @@ __global__ void __launch_bounds__(TX* TY) k_momentum(GridDev g, const double* __
   }
   const long pstride[3] = {(long)ny * (nx + 1), (long)(ny + 1) * nx, (long)ny * nx};
 
-  // Plane loads go to registers first and are written to LDS PF steps later, so
-  // the next PF planes are in flight while the current one is computed.
-  double r0[6][PER], r1[6][PER];
+  // Plane loads go to registers first and are written to LDS one step later, so
+  // the next plane is in flight while the current one is computed.
+  double r0[6][PER];
   auto load = [&](double(&reg)[6][PER], int k) {
     const bool kin_uv = (k >= 0) & (k < nz), kin_w = (k > 0) & (k < nz);
 #pragma unroll
@@ -110,10 +110,23 @@ __global__ void __launch_bounds__(TX* TY) k_momentum(GridDev g, const double* __
   const double rdy0 = (j < ny) ? g.y.rd[j] : 0.0, rdym = (j >= 1 && j - 1 < ny) ? g.y.rd[j - 1] : 0.0;
   const double rddy0 = (j <= ny) ? g.y.rdd[j] : 0.0, rddy1 = (j + 1 <= ny) ? g.y.rdd[j + 1] : 0.0;
 
+  double cm[6], c0[6], cp[6];
   auto compute = [&](int k) {
     const int pm = (k + 2) % 3, p0 = k % 3, pp = (k + 1) % 3;  // planes k-1, k, k+1
     // S(arr, plane, dj, di)
 #define S(arr, pl, dj, di) sm[arr][pl][(ty + 1 + (dj)) * MPX + (tx + 1 + (di))]
+    // own-column values of planes k-1 and k are carried in registers from the
+    // previous steps; only plane k+1's is read here
+    if (k == kb) {
+#pragma unroll
+      for (int arr = 0; arr < 6; ++arr) {
+        cm[arr] = S(arr, pm, 0, 0);
+        c0[arr] = S(arr, p0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int arr = 0; arr < 6; ++arr) cp[arr] = S(arr, pp, 0, 0);
+
     const double thz0 = g.z.th[k], thz1 = (k + 1 <= nz) ? g.z.th[k + 1] : 0.0;
     const double rdz0 = (k < nz) ? g.z.rd[k] : 0.0, rdzm = (k >= 1) ? g.z.rd[k - 1] : 0.0;
     const double rddz0 = g.z.rdd[k], rddz1 = (k + 1 <= nz) ? g.z.rdd[k + 1] : 0.0;
@@ -122,44 +135,44 @@ __global__ void __launch_bounds__(TX* TY) k_momentum(GridDev g, const double* __
     if (k < nz && j < ny && i <= nx) {
       double val = 0.0;
       if (i >= 1 && i <= nx - 1) {
-        const double bc = S(3, p0, 0, 0);
+        const double bc = c0[3];
         double lap = ((S(3, p0, 0, 1) - bc) * rdx0 - (bc - S(3, p0, 0, -1)) * rdxm) * rddx0;
         lap += ((S(3, p0, 1, 0) - bc) * rddy1 - (bc - S(3, p0, -1, 0)) * rddy0) * rdy0;
-        lap += ((S(3, pp, 0, 0) - bc) * rddz1 - (bc - S(3, pm, 0, 0)) * rddz0) * rdz0;
-        const double ac = S(0, p0, 0, 0);
+        lap += ((cp[3] - bc) * rddz1 - (bc - cm[3]) * rddz0) * rdz0;
+        const double ac = c0[0];
         const double am = 0.5 * (S(0, p0, 0, -1) + ac), ap = 0.5 * (ac + S(0, p0, 0, 1));
         const double bm = 0.5 * (S(3, p0, 0, -1) + bc), bp = 0.5 * (bc + S(3, p0, 0, 1));
         double conv = 2.0 * (ap * bp - am * bm) * rddx0;
         // edges (xf[i], yf[j + dj])
         double e0, e1;
         {
-          const double av = lerp(S(1, p0, 0, -1), S(1, p0, 0, 0), thx0);
-          const double bv = lerp(S(4, p0, 0, -1), S(4, p0, 0, 0), thx0);
-          const double au = lerp(S(0, p0, -1, 0), S(0, p0, 0, 0), thy0);
-          const double bu = lerp(S(3, p0, -1, 0), S(3, p0, 0, 0), thy0);
+          const double av = lerp(S(1, p0, 0, -1), c0[1], thx0);
+          const double bv = lerp(S(4, p0, 0, -1), c0[4], thx0);
+          const double au = lerp(S(0, p0, -1, 0), c0[0], thy0);
+          const double bu = lerp(S(3, p0, -1, 0), c0[3], thy0);
           e0 = av * bu + bv * au;
         }
         {
           const double av = lerp(S(1, p0, 1, -1), S(1, p0, 1, 0), thx0);
           const double bv = lerp(S(4, p0, 1, -1), S(4, p0, 1, 0), thx0);
-          const double au = lerp(S(0, p0, 0, 0), S(0, p0, 1, 0), thy1);
-          const double bu = lerp(S(3, p0, 0, 0), S(3, p0, 1, 0), thy1);
+          const double au = lerp(c0[0], S(0, p0, 1, 0), thy1);
+          const double bu = lerp(c0[3], S(3, p0, 1, 0), thy1);
           e1 = av * bu + bv * au;
         }
         conv += (e1 - e0) * rdy0;
         // edges (xf[i], zf[k + dk])
         {
-          const double aw = lerp(S(2, p0, 0, -1), S(2, p0, 0, 0), thx0);
-          const double bw = lerp(S(5, p0, 0, -1), S(5, p0, 0, 0), thx0);
-          const double au = lerp(S(0, pm, 0, 0), S(0, p0, 0, 0), thz0);
-          const double bu = lerp(S(3, pm, 0, 0), S(3, p0, 0, 0), thz0);
+          const double aw = lerp(S(2, p0, 0, -1), c0[2], thx0);
+          const double bw = lerp(S(5, p0, 0, -1), c0[5], thx0);
+          const double au = lerp(cm[0], c0[0], thz0);
+          const double bu = lerp(cm[3], c0[3], thz0);
           e0 = aw * bu + bw * au;
         }
         {
-          const double aw = lerp(S(2, pp, 0, -1), S(2, pp, 0, 0), thx0);
-          const double bw = lerp(S(5, pp, 0, -1), S(5, pp, 0, 0), thx0);
-          const double au = lerp(S(0, p0, 0, 0), S(0, pp, 0, 0), thz1);
-          const double bu = lerp(S(3, p0, 0, 0), S(3, pp, 0, 0), thz1);
+          const double aw = lerp(S(2, pp, 0, -1), cp[2], thx0);
+          const double bw = lerp(S(5, pp, 0, -1), cp[5], thx0);
+          const double au = lerp(c0[0], cp[0], thz1);
+          const double bu = lerp(c0[3], cp[3], thz1);
           e1 = aw * bu + bw * au;
         }
         conv += (e1 - e0) * rdz0;
@@ -172,44 +185,44 @@ __global__ void __launch_bounds__(TX* TY) k_momentum(GridDev g, const double* __
     if (k < nz && j <= ny && i < nx) {
       double val = 0.0;
       if (j >= 1 && j <= ny - 1) {
-        const double bc = S(4, p0, 0, 0);
+        const double bc = c0[4];
         double lap = ((S(4, p0, 1, 0) - bc) * rdy0 - (bc - S(4, p0, -1, 0)) * rdym) * rddy0;
         lap += ((S(4, p0, 0, 1) - bc) * rddx1 - (bc - S(4, p0, 0, -1)) * rddx0) * rdx0;
-        lap += ((S(4, pp, 0, 0) - bc) * rddz1 - (bc - S(4, pm, 0, 0)) * rddz0) * rdz0;
+        lap += ((cp[4] - bc) * rddz1 - (bc - cm[4]) * rddz0) * rdz0;
         double e0, e1;
         // edges (xf[i + di], yf[j])
         {
-          const double au = lerp(S(0, p0, -1, 0), S(0, p0, 0, 0), thy0);
-          const double bu = lerp(S(3, p0, -1, 0), S(3, p0, 0, 0), thy0);
-          const double av = lerp(S(1, p0, 0, -1), S(1, p0, 0, 0), thx0);
-          const double bv = lerp(S(4, p0, 0, -1), S(4, p0, 0, 0), thx0);
+          const double au = lerp(S(0, p0, -1, 0), c0[0], thy0);
+          const double bu = lerp(S(3, p0, -1, 0), c0[3], thy0);
+          const double av = lerp(S(1, p0, 0, -1), c0[1], thx0);
+          const double bv = lerp(S(4, p0, 0, -1), c0[4], thx0);
           e0 = au * bv + bu * av;
         }
         {
           const double au = lerp(S(0, p0, -1, 1), S(0, p0, 0, 1), thy0);
           const double bu = lerp(S(3, p0, -1, 1), S(3, p0, 0, 1), thy0);
-          const double av = lerp(S(1, p0, 0, 0), S(1, p0, 0, 1), thx1);
-          const double bv = lerp(S(4, p0, 0, 0), S(4, p0, 0, 1), thx1);
+          const double av = lerp(c0[1], S(1, p0, 0, 1), thx1);
+          const double bv = lerp(c0[4], S(4, p0, 0, 1), thx1);
           e1 = au * bv + bu * av;
         }
         double conv = (e1 - e0) * rdx0;
-        const double ac = S(1, p0, 0, 0);
+        const double ac = c0[1];
         const double am = 0.5 * (S(1, p0, -1, 0) + ac), ap = 0.5 * (ac + S(1, p0, 1, 0));
         const double bm = 0.5 * (S(4, p0, -1, 0) + bc), bp = 0.5 * (bc + S(4, p0, 1, 0));
         conv += 2.0 * (ap * bp - am * bm) * rddy0;
         // edges (yf[j], zf[k + dk])
         {
-          const double aw = lerp(S(2, p0, -1, 0), S(2, p0, 0, 0), thy0);
-          const double bw = lerp(S(5, p0, -1, 0), S(5, p0, 0, 0), thy0);
-          const double av = lerp(S(1, pm, 0, 0), S(1, p0, 0, 0), thz0);
-          const double bv = lerp(S(4, pm, 0, 0), S(4, p0, 0, 0), thz0);
+          const double aw = lerp(S(2, p0, -1, 0), c0[2], thy0);
+          const double bw = lerp(S(5, p0, -1, 0), c0[5], thy0);
+          const double av = lerp(cm[1], c0[1], thz0);
+          const double bv = lerp(cm[4], c0[4], thz0);
           e0 = aw * bv + bw * av;
         }
         {
-          const double aw = lerp(S(2, pp, -1, 0), S(2, pp, 0, 0), thy0);
-          const double bw = lerp(S(5, pp, -1, 0), S(5, pp, 0, 0), thy0);
-          const double av = lerp(S(1, p0, 0, 0), S(1, pp, 0, 0), thz1);
-          const double bv = lerp(S(4, p0, 0, 0), S(4, pp, 0, 0), thz1);
+          const double aw = lerp(S(2, pp, -1, 0), cp[2], thy0);
+          const double bw = lerp(S(5, pp, -1, 0), cp[5], thy0);
+          const double av = lerp(c0[1], cp[1], thz1);
+          const double bv = lerp(c0[4], cp[4], thz1);
           e1 = aw * bv + bw * av;
         }
         conv += (e1 - e0) * rdz0;
@@ -222,52 +235,57 @@ __global__ void __launch_bounds__(TX* TY) k_momentum(GridDev g, const double* __
     if (k <= nz && j < ny && i < nx) {
       double val = 0.0;
       if (k >= 1 && k <= nz - 1) {
-        const double bc = S(5, p0, 0, 0);
-        double lap = ((S(5, pp, 0, 0) - bc) * rdz0 - (bc - S(5, pm, 0, 0)) * rdzm) * rddz0;
+        const double bc = c0[5];
+        double lap = ((cp[5] - bc) * rdz0 - (bc - cm[5]) * rdzm) * rddz0;
         lap += ((S(5, p0, 0, 1) - bc) * rddx1 - (bc - S(5, p0, 0, -1)) * rddx0) * rdx0;
         lap += ((S(5, p0, 1, 0) - bc) * rddy1 - (bc - S(5, p0, -1, 0)) * rddy0) * rdy0;
         double e0, e1;
         // edges (xf[i + di], zf[k])
         {
-          const double au = lerp(S(0, pm, 0, 0), S(0, p0, 0, 0), thz0);
-          const double bu = lerp(S(3, pm, 0, 0), S(3, p0, 0, 0), thz0);
-          const double aw = lerp(S(2, p0, 0, -1), S(2, p0, 0, 0), thx0);
-          const double bw = lerp(S(5, p0, 0, -1), S(5, p0, 0, 0), thx0);
+          const double au = lerp(cm[0], c0[0], thz0);
+          const double bu = lerp(cm[3], c0[3], thz0);
+          const double aw = lerp(S(2, p0, 0, -1), c0[2], thx0);
+          const double bw = lerp(S(5, p0, 0, -1), c0[5], thx0);
           e0 = au * bw + bu * aw;
         }
         {
           const double au = lerp(S(0, pm, 0, 1), S(0, p0, 0, 1), thz0);
           const double bu = lerp(S(3, pm, 0, 1), S(3, p0, 0, 1), thz0);
-          const double aw = lerp(S(2, p0, 0, 0), S(2, p0, 0, 1), thx1);
-          const double bw = lerp(S(5, p0, 0, 0), S(5, p0, 0, 1), thx1);
+          const double aw = lerp(c0[2], S(2, p0, 0, 1), thx1);
+          const double bw = lerp(c0[5], S(5, p0, 0, 1), thx1);
           e1 = au * bw + bu * aw;
         }
         double conv = (e1 - e0) * rdx0;
         // edges (yf[j + dj], zf[k])
         {
-          const double av = lerp(S(1, pm, 0, 0), S(1, p0, 0, 0), thz0);
-          const double bv = lerp(S(4, pm, 0, 0), S(4, p0, 0, 0), thz0);
-          const double aw = lerp(S(2, p0, -1, 0), S(2, p0, 0, 0), thy0);
-          const double bw = lerp(S(5, p0, -1, 0), S(5, p0, 0, 0), thy0);
+          const double av = lerp(cm[1], c0[1], thz0);
+          const double bv = lerp(cm[4], c0[4], thz0);
+          const double aw = lerp(S(2, p0, -1, 0), c0[2], thy0);
+          const double bw = lerp(S(5, p0, -1, 0), c0[5], thy0);
           e0 = av * bw + bv * aw;
         }
         {
           const double av = lerp(S(1, pm, 1, 0), S(1, p0, 1, 0), thz0);
           const double bv = lerp(S(4, pm, 1, 0), S(4, p0, 1, 0), thz0);
-          const double aw = lerp(S(2, p0, 0, 0), S(2, p0, 1, 0), thy1);
-          const double bw = lerp(S(5, p0, 0, 0), S(5, p0, 1, 0), thy1);
+          const double aw = lerp(c0[2], S(2, p0, 1, 0), thy1);
+          const double bw = lerp(c0[5], S(5, p0, 1, 0), thy1);
           e1 = av * bw + bv * aw;
         }
         conv += (e1 - e0) * rdy0;
-        const double ac = S(2, p0, 0, 0);
-        const double am = 0.5 * (S(2, pm, 0, 0) + ac), ap = 0.5 * (ac + S(2, pp, 0, 0));
-        const double bm = 0.5 * (S(5, pm, 0, 0) + bc), bp = 0.5 * (bc + S(5, pp, 0, 0));
+        const double ac = c0[2];
+        const double am = 0.5 * (cm[2] + ac), ap = 0.5 * (ac + cp[2]);
+        const double bm = 0.5 * (cm[5] + bc), bp = 0.5 * (bc + cp[5]);
         conv += 2.0 * (ap * bp - am * bm) * rddz0;
         val = rre * lap - s * conv;
       }
       out[nu + nv + ((size_t)k * ny + j) * nx + i] = val;
     }
 #undef S
+#pragma unroll
+    for (int arr = 0; arr < 6; ++arr) {
+      cm[arr] = c0[arr];
+      c0[arr] = cp[arr];
+    }
   };
 
   load(r0, kb - 1);
@@ -275,30 +293,12 @@ __global__ void __launch_bounds__(TX* TY) k_momentum(GridDev g, const double* __
   load(r0, kb);
   store(r0, kb);
   load(r0, kb + 1);
-  if (PF == 1) {
-    for (int k = kb; k < ke; ++k) {
-      store(r0, k + 1);
-      __syncthreads();
-      if (k + 2 <= ke) load(r0, k + 2);
-      compute(k);
-      __syncthreads();
-    }
-  } else {
-    // two planes in flight: r0 carries planes kb+1, kb+3, ...; r1 planes kb+2, kb+4, ...
-    if (kb + 2 <= ke) load(r1, kb + 2);
-    for (int k = kb; k < ke; k += 2) {
-      store(r0, k + 1);
-      __syncthreads();
-      if (k + 3 <= ke) load(r0, k + 3);
-      compute(k);
-      __syncthreads();
-      if (k + 1 >= ke) break;
-      store(r1, k + 2);
-      __syncthreads();
-      if (k + 4 <= ke) load(r1, k + 4);
-      compute(k + 1);
-      __syncthreads();
-    }
+  for (int k = kb; k < ke; ++k) {
+    store(r0, k + 1);
+    __syncthreads();
+    if (k + 2 <= ke) load(r0, k + 2);
+    compute(k);
+    __syncthreads();
   }
 }
 
@@ -371,7 +371,7 @@ __global__ void __launch_bounds__(256) k_correct(GridDev g, const double* __rest
 
 // ==================================================================== launchers
 // Tile of the momentum stencil: TX x TY threads, kMomChunk planes per block.
-constexpr int kMomTX = 16, kMomTY = 16, kMomChunk = 24, kMomPF = 1;
+constexpr int kMomTX = 16, kMomTY = 8, kMomChunk = 24;
 
 hipError_t launch_momentum(const GridDev& g, const double* a, const double* b, double* out, double rre, double s,
                            bool lid, double lid_u, double lid_v, hipStream_t st) {
@@ -380,10 +380,10 @@ hipError_t launch_momentum(const GridDev& g, const double* a, const double* b, d
   const int nbz = (int)blocks_for(nz + 1, kMomChunk);
   const dim3 grid(nbx * nby * nbz), block(kMomTX * kMomTY);
   if (lid)
-    hipLaunchKernelGGL((k_momentum<true, kMomTX, kMomTY, kMomPF>), grid, block, 0, st, g, a, b, out, rre, s, lid_u, lid_v,
+    hipLaunchKernelGGL((k_momentum<true, kMomTX, kMomTY>), grid, block, 0, st, g, a, b, out, rre, s, lid_u, lid_v,
                        kMomChunk, nbx, nby);
   else
-    hipLaunchKernelGGL((k_momentum<false, kMomTX, kMomTY, kMomPF>), grid, block, 0, st, g, a, b, out, rre, s, 0.0, 0.0,
+    hipLaunchKernelGGL((k_momentum<false, kMomTX, kMomTY>), grid, block, 0, st, g, a, b, out, rre, s, 0.0, 0.0,
                        kMomChunk, nbx, nby);
   return hipGetLastError();
 }

@@ -9,6 +9,12 @@ namespace lk {
 
 typedef __bf16 bf16;
 
+// GEMM reduction layout of a 3x3x3 convolution with cin input channels: chunks of
+// conv_cc(cin) channels, each holding (tap, channel) pairs padded to a multiple of 32.
+__host__ __device__ constexpr int conv_cc(int cin) { return cin <= 16 ? cin : (cin % 32 == 0 ? 32 : 16); }
+__host__ __device__ constexpr int conv_kpc(int cin) { return (27 * conv_cc(cin) + 31) / 32 * 32; }
+__host__ __device__ constexpr int conv_kp(int cin) { return cin / conv_cc(cin) * conv_kpc(cin); }
+
 // 3x3x3 convolution of layer `layer` (0 enc1, 1 enc2, 2 bottleneck, 3 dec2, 4 dec1).
 // Forward: out = relu(conv(in) + bias) in BF16; `a` is the half-resolution source of
 // a decoder's concatenated input (nullptr otherwise), `b` the full-resolution one.

@@ -38,7 +38,14 @@ __device__ __forceinline__ bf16x8 load8(const bf16* p, bool ok) {
 __device__ __forceinline__ float bf2f(bf16 h) { return static_cast<float>(h); }
 __device__ __forceinline__ bf16 f2bf(float f) { return static_cast<bf16>(f); }
 
-__device__ __forceinline__ int kpad(int cin) { return (27 * cin + 31) / 32 * 32; }
+// Workgroups are dispatched round-robin over the 8 XCDs; renumber so that each XCD
+// receives a contiguous range of tiles and neighbouring tiles share an L2.
+__device__ __forceinline__ int xcd_tile(int bid, int nb) {
+  constexpr int NX = 8;
+  const int xcd = bid % NX, local = bid / NX;
+  const int per = nb / NX, rem = nb % NX;
+  return xcd < rem ? xcd * (per + 1) + local : rem * (per + 1) + (xcd - rem) * per + local;
+}
 
 // ------------------------------------------------------------------ convolution
 // out[p][co] = sum_k W[co][k] X_k[p] for the D x H x W voxel grid.  The input is
@@ -46,82 +53,117 @@ __device__ __forceinline__ int kpad(int cin) { return (27 * cin + 31) / 32 * 32;
 // (CA channels, read at (z>>1, y>>1, x>>1): nearest upsampling) and a
 // full-resolution tensor B (CIN - CA channels).  OUTF = false: out = relu(acc +
 // bias) in BF16; OUTF = true: out = acc in FP32 (backward data pass).
-// One wave computes RB x 16 consecutive voxels for all COUT channels.
+//
+// A block computes a 16 x 4 x 4 (x, y, z) brick of output voxels, one z-plane per
+// wave, four 16-voxel rows per wave.  The 18 x 6 x 6 input brick is staged in LDS
+// CC channels at a time (channel-group major, so the 16 lanes of one MFMA row group
+// read one contiguous 256-byte LDS line), and all 27 taps read their A fragments from it: each
+// input value is fetched from memory about 2.5 times instead of 27.  The weights
+// are ordered (channel chunk, tap, channel) to match: one 32-wide k step covers
+// 32 / CC taps of one chunk.
+constexpr int kCTX = 16, kCTY = 4, kCTZ = 4;
+
 template <int CIN, int COUT, int CA, bool OUTF>
 __global__ __launch_bounds__(kBlock) void k_conv(const bf16* __restrict__ srcA, const bf16* __restrict__ srcB,
                                                  const bf16* __restrict__ wt, const float* __restrict__ bias,
                                                  void* __restrict__ out, int D, int H, int W) {
-  constexpr int RB = 4;
-  constexpr int NB = COUT / 16;
-  constexpr int CB = CIN - CA;
-  constexpr int KP = (27 * CIN + 31) / 32 * 32;
-  const long P = (long)D * H * W;
-  const int lane = threadIdx.x & 63;
-  const int g = lane >> 4;
-  const int r16 = lane & 15;
-  const long base = ((long)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)) * (RB * 16);
-  int vz[RB], vy[RB], vx[RB];
-  bool valid[RB];
-#pragma unroll
-  for (int rb = 0; rb < RB; ++rb) {
-    const long p = base + rb * 16 + r16;
-    valid[rb] = p < P;
-    const long q = valid[rb] ? p : 0;
-    vx[rb] = (int)(q % W);
-    vy[rb] = (int)((q / W) % H);
-    vz[rb] = (int)(q / ((long)W * H));
-  }
+  constexpr int CC = conv_cc(CIN), NCH = CIN / CC, KPC = conv_kpc(CIN), KP = conv_kp(CIN);
+  constexpr int NB = COUT / 16, CB = CIN - CA;
+  constexpr int PX = kCTX + 2, PY = kCTY + 2, PZ = kCTZ + 2, NV = PX * PY * PZ;
+  constexpr int C8 = CC / 8;
+  // staged brick, channel-group major: [CC / 8][voxel][8], so 16 consecutive voxels of
+  // one channel group are 256 contiguous bytes (one conflict-free LDS read)
+  __shared__ __attribute__((aligned(16))) bf16 tile[C8 * NV * 8];
+  const int nbx = (W + kCTX - 1) / kCTX, nby = (H + kCTY - 1) / kCTY;
+  const int t = xcd_tile(blockIdx.x, gridDim.x);
+  const int x0 = (t % nbx) * kCTX, y0 = ((t / nbx) % nby) * kCTY, z0 = (t / (nbx * nby)) * kCTZ;
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63, g = lane >> 4, r16 = lane & 15;
   const int H2 = H >> 1, W2 = W >> 1;
-  floatx4 acc[RB][NB];
+  floatx4 acc[4][NB];
 #pragma unroll
-  for (int rb = 0; rb < RB; ++rb)
+  for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) acc[rb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
-  const bf16* wrow = wt + (long)r16 * KP + 8 * g;
-  for (int kc = 0; kc < KP; kc += 32) {
-    const int k = kc + 8 * g;
-    const int tap = k / CIN;
-    const int ci = k - tap * CIN;
-    const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
-    const bool tap_ok = tap < 27;
-    bf16x8 a[RB];
-#pragma unroll
-    for (int rb = 0; rb < RB; ++rb) {
-      const int z = vz[rb] + dz, y = vy[rb] + dy, x = vx[rb] + dx;
-      const bool ok = valid[rb] && tap_ok && (unsigned)z < (unsigned)D && (unsigned)y < (unsigned)H &&
-                      (unsigned)x < (unsigned)W;
-      const int zc = ok ? z : 0, yc = ok ? y : 0, xc = ok ? x : 0;
+  for (int ch = 0; ch < NCH; ++ch) {
+    // stage the input brick of this channel chunk, 8 channels (16 bytes) per load
+    for (int e = tid; e < NV * C8; e += kBlock) {
+      const int c8 = e / NV, v = e - (e / NV) * NV;
+      const int vx = v % PX, vy = (v / PX) % PY, vz = v / (PX * PY);
+      const int gx = x0 - 1 + vx, gy = y0 - 1 + vy, gz = z0 - 1 + vz;
+      const bool ok = (unsigned)gx < (unsigned)W && (unsigned)gy < (unsigned)H && (unsigned)gz < (unsigned)D;
+      const int xc = ok ? gx : 0, yc = ok ? gy : 0, zc = ok ? gz : 0;
+      const int ci = ch * CC + 8 * c8;
       const bf16* ptr;
       if (CA > 0 && ci < CA)
         ptr = srcA + (((long)(zc >> 1) * H2 + (yc >> 1)) * W2 + (xc >> 1)) * CA + ci;
       else
         ptr = srcB + (((long)zc * H + yc) * W + xc) * CB + (ci - CA);
-      a[rb] = load8(ptr, ok);
+      *reinterpret_cast<bf16x8*>(&tile[(c8 * NV + v) * 8]) = load8(ptr, ok);
     }
+    __syncthreads();
+    const bf16* wch = wt + (long)r16 * KP + ch * KPC + 8 * g;
+    // A fragments (LDS) of step s + 1 and B fragments (weights, from L1/L2) of step
+    // s + 3 are fetched while step s's MFMAs run
+    constexpr int NS = KPC / 32, BD = 4;
+    auto fetch_a = [&](int s, bf16x8 (&a)[4]) {
+      // padding steps (tap >= 27) read tap 0: their weights are zero and staged values finite
+      const int k = 32 * s + 8 * g;
+      const int tap = k / CC, ci = k - (k / CC) * CC;
+      const int tc = tap < 27 ? tap : 0;
+      const int dz = tc / 9, dy = (tc / 3) % 3, dx = tc % 3;  // offsets + 1 into the padded brick
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-      const bf16x8 b = *reinterpret_cast<const bf16x8*>(wrow + (long)nb * 16 * KP + kc);
+      for (int rb = 0; rb < 4; ++rb) {
+        const int v = ((wv + dz) * PY + (rb + dy)) * PX + (r16 + dx);
+        a[rb] = *reinterpret_cast<const bf16x8*>(&tile[((ci >> 3) * NV + v) * 8]);
+      }
+    };
+    bf16x8 bq[BD][NB];
 #pragma unroll
-      for (int rb = 0; rb < RB; ++rb) acc[rb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rb], b, acc[rb][nb], 0, 0, 0);
+    for (int s = 0; s < BD - 1; ++s)
+      if (s < NS)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) bq[s][nb] = *reinterpret_cast<const bf16x8*>(wch + (long)nb * 16 * KP + 32 * s);
+    bf16x8 a0[4], a1[4];
+    fetch_a(0, a0);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      bf16x8(&ac)[4] = (s & 1) ? a1 : a0;
+      bf16x8(&an)[4] = (s & 1) ? a0 : a1;
+      if (s + 1 < NS) fetch_a(s + 1, an);
+      if (s + BD - 1 < NS)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+          bq[(s + BD - 1) % BD][nb] = *reinterpret_cast<const bf16x8*>(wch + (long)nb * 16 * KP + 32 * (s + BD - 1));
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+          acc[rb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ac[rb], bq[s % BD][nb], acc[rb][nb], 0, 0, 0);
     }
+    __syncthreads();
   }
+  // result rows 4g + j of a 16-voxel row are x0 + 4g + j; columns are channels
+  const int z = z0 + wv;
 #pragma unroll
-  for (int rb = 0; rb < RB; ++rb)
+  for (int rb = 0; rb < 4; ++rb) {
+    const int y = y0 + rb;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const long p = base + rb * 16 + 4 * g + j;
-      if (p >= P) continue;
+      const int x = x0 + 4 * g + j;
+      if (x >= W || y >= H || z >= D) continue;
+      const long p = ((long)z * H + y) * W + x;
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
         const int co = nb * 16 + r16;
         if (OUTF) {
           static_cast<float*>(out)[p * COUT + co] = acc[rb][nb][j];
         } else {
-          const float v = acc[rb][nb][j] + bias[co];
-          static_cast<bf16*>(out)[p * COUT + co] = f2bf(v > 0.f ? v : 0.f);
+          const float val = acc[rb][nb][j] + bias[co];
+          static_cast<bf16*>(out)[p * COUT + co] = f2bf(val > 0.f ? val : 0.f);
         }
       }
     }
+  }
 }
 
 // --------------------------------------------------------------- weight gradient
@@ -372,24 +414,27 @@ __global__ void k_adam(float* __restrict__ w, const float* __restrict__ g, float
   w[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
 }
 
-// BF16 GEMM weights of a 3x3x3 layer from its FP32 master W[co][27][cin_real]:
-// forward [cout][KP] with k = tap*cinp + ci; transposed-flipped for the backward
-// data pass [cin][KPt] with k = tap*cout + co holding W[co][26 - tap][ci].
+// BF16 GEMM weights of a 3x3x3 layer from its FP32 master W[co][27][cin_real], in
+// the (channel chunk, tap, channel) order of k_conv: forward [cout][conv_kp(cinp)];
+// transposed-flipped for the backward data pass [cin][conv_kp(cout)] holding
+// W[co][26 - tap][ci] at (chunk of co, tap, co).
 __global__ void k_prep_fwd(const float* __restrict__ w, bf16* __restrict__ out, int cout, int cinp, int cin_real) {
-  const int KP = kpad(cinp);
+  const int CC = conv_cc(cinp), KPC = conv_kpc(cinp), KP = conv_kp(cinp);
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (long)cout * KP) return;
   const int k = (int)(e % KP), co = (int)(e / KP);
-  const int tap = k / cinp, ci = k % cinp;
+  const int ch = k / KPC, r = k % KPC;
+  const int tap = r / CC, ci = ch * CC + r % CC;
   out[e] = f2bf(tap < 27 && ci < cin_real ? w[((long)co * 27 + tap) * cin_real + ci] : 0.f);
 }
 
 __global__ void k_prep_bwd(const float* __restrict__ w, bf16* __restrict__ out, int cout, int cin) {
-  const int KP = kpad(cout);
+  const int CC = conv_cc(cout), KPC = conv_kpc(cout), KP = conv_kp(cout);
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (long)cin * KP) return;
   const int k = (int)(e % KP), ci = (int)(e / KP);
-  const int tap = k / cout, co = k % cout;
+  const int ch = k / KPC, r = k % KPC;
+  const int tap = r / CC, co = ch * CC + r % CC;
   out[e] = f2bf(tap < 27 ? w[((long)co * 27 + (26 - tap)) * cin + ci] : 0.f);
 }
 
@@ -523,8 +568,8 @@ unsigned blocks(long n, int b = kBlock) { return (unsigned)((n + b - 1) / b); }
 // ------------------------------------------------------------------ launchers
 hipError_t nn_conv(int layer, bool backward, const bf16* a, const bf16* b, const bf16* wt, const float* bias, void* out,
                    int D, int H, int W, hipStream_t st) {
-  const long P = (long)D * H * W;
-  const dim3 grid(blocks(P, 256)), blk(kBlock);  // 4 waves x 64 voxels
+  const long tiles = (long)((W + kCTX - 1) / kCTX) * ((H + kCTY - 1) / kCTY) * ((D + kCTZ - 1) / kCTZ);
+  const dim3 grid((unsigned)tiles), blk(kBlock);  // one 16 x 4 x 4 output brick per block
 #define CONV(CIN, COUT, CA, OUTF) \
   hipLaunchKernelGGL((k_conv<CIN, COUT, CA, OUTF>), grid, blk, 0, st, a, b, wt, bias, out, D, H, W)
   if (!backward) {
@@ -623,10 +668,10 @@ hipError_t nn_adam(float* w, const float* g, float* m, float* v, long n, float l
 }
 
 hipError_t nn_prep(const float* w, bf16* fwd, bf16* bwd, int cout, int cinp, int cin_real, hipStream_t st) {
-  const int KP = (27 * cinp + 31) / 32 * 32;
+  const int KP = conv_kp(cinp);
   hipLaunchKernelGGL(k_prep_fwd, dim3(blocks((long)cout * KP)), dim3(kBlock), 0, st, w, fwd, cout, cinp, cin_real);
   if (bwd) {
-    const int KPt = (27 * cout + 31) / 32 * 32;
+    const int KPt = conv_kp(cout);
     hipLaunchKernelGGL(k_prep_bwd, dim3(blocks((long)cin_real * KPt)), dim3(kBlock), 0, st, w, bwd, cout, cin_real);
   }
   return hipGetLastError();

@@ -34,7 +34,6 @@ long woff(int l) {
 }
 long boff(int l) { return woff(l) + (long)kLayers[l].cout * kLayers[l].taps * kLayers[l].cin; }
 long nparams() { return woff(6); }
-int kpad(int c) { return (27 * c + 31) / 32 * 32; }
 
 uint64_t splitmix(uint64_t& s) {
   uint64_t z = (s += 0x9E3779B97F4A7C15ull);
@@ -317,8 +316,8 @@ int lc_net_create(lc_net** out, uint64_t seed) {
   const size_t pbytes = al(n->np * sizeof(float));
   size_t wbytes = 0;
   for (int l = 0; l < 5; ++l) {
-    wbytes += al((size_t)kLayers[l].cout * kpad(kLayers[l].cinp) * sizeof(bf16));
-    if (l > 0) wbytes += al((size_t)kLayers[l].cin * kpad(kLayers[l].cout) * sizeof(bf16));
+    wbytes += al((size_t)kLayers[l].cout * lk::conv_kp(kLayers[l].cinp) * sizeof(bf16));
+    if (l > 0) wbytes += al((size_t)kLayers[l].cin * lk::conv_kp(kLayers[l].cout) * sizeof(bf16));
   }
   if (hipMalloc(&n->wmem, 4 * pbytes + wbytes) != hipSuccess || hipMalloc(&n->dpart, kPartBlocks * 3 * sizeof(double)) ||
       hipHostMalloc(&n->hpart, kPartBlocks * 3 * sizeof(double), 0) != hipSuccess) {
@@ -335,10 +334,10 @@ int lc_net_create(lc_net** out, uint64_t seed) {
   p += 4 * pbytes;
   for (int l = 0; l < 5; ++l) {
     n->wf[l] = reinterpret_cast<bf16*>(p);
-    p += al((size_t)kLayers[l].cout * kpad(kLayers[l].cinp) * sizeof(bf16));
+    p += al((size_t)kLayers[l].cout * lk::conv_kp(kLayers[l].cinp) * sizeof(bf16));
     if (l > 0) {
       n->wb[l] = reinterpret_cast<bf16*>(p);
-      p += al((size_t)kLayers[l].cin * kpad(kLayers[l].cout) * sizeof(bf16));
+      p += al((size_t)kLayers[l].cin * lk::conv_kp(kLayers[l].cout) * sizeof(bf16));
     }
   }
   // He-normal weights (Box-Muller on a SplitMix64 stream), zero biases

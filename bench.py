@@ -110,7 +110,17 @@ def train_guess(lk, torch, n, steps):
                  "loss_last30": float(sum(hist[-30:]) / max(1, min(30, steps)))}
 
 
-def kernel_table(prof, n):
+def transform_flops(n, lines, symmetric):
+    """FLOPs of one line transform of `lines` lines of length n: a dense n x n product,
+    or on a mirror-symmetric axis the two half-size products (forward: he^2 + ho^2 per
+    line; backward: he (he + ho)), averaged over the forward and backward launch."""
+    if not symmetric:
+        return 2.0 * n * n * lines
+    he, ho = (n + 1) // 2, n // 2
+    return 2.0 * lines * 0.5 * ((he * he + ho * ho) + he * (he + ho))
+
+
+def kernel_table(prof, n, symmetric=True):
     """Per-kernel average durations and algorithmic rates."""
     nx = ny = nz = n
     ncell = nx * ny * nz
@@ -120,9 +130,9 @@ def kernel_table(prof, n):
         "momentum": ("hbm", 3 * fu),             # read U, v; write w
         "divergence": ("hbm", fu + fp),          # read v; write r
         "correct": ("hbm", 2 * fu + 2 * fp),     # read w, phi; write v, p
-        "tp_x": ("alu", 2.0 * nx * nx * ny * nz),
-        "tp_y": ("alu", 2.0 * ny * ny * nx * nz),
-        "tp_z": ("alu", 2.0 * nz * nz * nx * ny),
+        "tp_x": ("alu", transform_flops(nx, ny * nz, symmetric)),
+        "tp_y": ("alu", transform_flops(ny, nx * nz, symmetric)),
+        "tp_z": ("alu", transform_flops(nz, nx * ny, symmetric)),
         "eigscale": ("hbm", 2 * fp),
     }
     table = {}
@@ -257,7 +267,7 @@ def main():
     time_form(ctx, torch, inputs, 0, a.steps, lk.FP64)
     prof = ctx.profile_read()
     ctx.profile(False)
-    table = kernel_table(prof, n)
+    table = kernel_table(prof, n, symmetric=True)  # the tanh grid is mirror-symmetric
     # the learned form's network forward pass (all layers), same method
     ctx.profile(True)
     time_form(ctx, torch, inputs, 0, min(a.steps, 5), lk.LEARNED)

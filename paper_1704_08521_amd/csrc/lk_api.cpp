@@ -1,6 +1,7 @@
 // C ABI of lidkrylov: context, grid, stencils, Poisson solve, SIMPLE projection.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -102,11 +103,14 @@ int upload_grid(lc_ctx* c) {
   }
   HIPCHK(c, hipMemcpyAsync(c->metric, host.data(), total * sizeof(double), hipMemcpyHostToDevice, c->stream));
 
-  // tensor-product factorization of each axis
+  // tensor-product factorization of each axis (full matrices, plus the parity-sorted
+  // half matrices of mirror-symmetric axes: at most 2.5 n^2 values each in both precisions)
   size_t mbytes = 0;
   for (int a = 0; a < 3; ++a) {
     const size_t nn = (size_t)n[a] * n[a];
-    mbytes += n[a] * sizeof(double) + 4 * nn * sizeof(double) + 4 * nn * sizeof(float);
+    const size_t half = 3 * nn;
+    mbytes += 2 * n[a] * sizeof(double) + 4 * nn * sizeof(double) + 4 * nn * sizeof(float) +
+              half * (sizeof(double) + sizeof(float));
   }
   if (!c->modes_mem) HIPCHK(c, hipMalloc(&c->modes_mem, mbytes));
   std::vector<char> mhost(mbytes);
@@ -147,6 +151,61 @@ int upload_grid(lc_ctx* c) {
     put_f(Bk, &M.Bk32);
     put_f(FT, &M.FT32);
     put_f(BkT, &M.BkT32);
+    // mirror symmetry: widths and centre distances equal under i -> m-1-i
+    const AxisHost& AH = c->ax[a];
+    bool sym = m >= 2;
+    double wmax = 0.0;
+    for (int i = 0; i < m; ++i) wmax = std::max(wmax, AH.d[i]);
+    for (int i = 0; i < m && sym; ++i) sym = std::fabs(AH.d[i] - AH.d[m - 1 - i]) <= 1e-12 * wmax;
+    for (int i = 0; i <= m && sym; ++i) sym = std::fabs(AH.dd[i] - AH.dd[m - i]) <= 1e-12 * wmax;
+    const int he = (m + 1) / 2, ho = m / 2;
+    std::vector<double> lam_e, lam_o, Sh_e, Sh_o;
+    if (sym && (!neumann_half_modes(m, AH.d.data(), AH.dd.data(), false, lam_e, Sh_e) ||
+                !neumann_half_modes(m, AH.d.data(), AH.dd.data(), true, lam_o, Sh_o)))
+      return fail(c, LC_EINVAL, "tridiagonal eigen-solver did not converge on axis %d (half problems)", a);
+    M.sym = sym;
+    M.he = he;
+    M.ho = ho;
+    if (sym) {
+      // parity-sorted modes: the he even ones (ascending, the null mode last), then the odd ones
+      const double r2 = std::sqrt(0.5);
+      const bool mid = (m % 2) == 1;
+      std::vector<double> lam_s(lam_e), h[8];
+      lam_s.insert(lam_s.end(), lam_o.begin(), lam_o.end());
+      c->zero_mode[a] = he - 1;
+      h[0].assign((size_t)he * he, 0.0);
+      h[1].assign((size_t)ho * ho, 0.0);
+      h[2].assign((size_t)he * he, 0.0);
+      h[3].assign((size_t)he * ho, 0.0);
+      // forward: c_k = sum_p A[k][p] fold(r)_p, fold = r_p + r_{m-1-p} (r_mid alone), r_p - r_{m-1-p}
+      for (int k = 0; k < he; ++k)
+        for (int p = 0; p < he; ++p) {
+          const double wgt = (mid && p == he - 1) ? 1.0 : r2;
+          h[0][(size_t)k * he + p] = Sh_e[(size_t)p * he + k] * AH.d[p] * wgt;
+          h[2][(size_t)p * he + k] = Sh_e[(size_t)p * he + k] * wgt;  // backward: phi_p from even modes
+        }
+      for (int k = 0; k < ho; ++k)
+        for (int p = 0; p < ho; ++p) {
+          h[1][(size_t)k * ho + p] = Sh_o[(size_t)p * ho + k] * AH.d[p] * r2;
+          h[3][(size_t)p * ho + k] = Sh_o[(size_t)p * ho + k] * r2;  // rows p < ho; the middle row stays 0
+        }
+      h[4].resize((size_t)he * he);
+      h[5].resize((size_t)ho * ho);
+      h[6].resize((size_t)he * he);
+      h[7].resize((size_t)ho * he);
+      for (int r = 0; r < he; ++r)
+        for (int i = 0; i < he; ++i) {
+          h[4][(size_t)i * he + r] = h[0][(size_t)r * he + i];
+          h[6][(size_t)r * he + i] = h[2][(size_t)i * he + r];
+        }
+      for (int r = 0; r < ho; ++r)
+        for (int i = 0; i < ho; ++i) h[5][(size_t)i * ho + r] = h[1][(size_t)r * ho + i];
+      for (int i = 0; i < he; ++i)
+        for (int r = 0; r < ho; ++r) h[7][(size_t)r * he + i] = h[3][(size_t)i * ho + r];
+      put_d(lam_s, &M.lam_s);
+      for (int q = 0; q < 8; ++q) put_d(h[q], &M.h64[q]);
+      for (int q = 0; q < 8; ++q) put_f(h[q], &M.h32[q]);
+    }
   }
   HIPCHK(c, hipMemcpyAsync(c->modes_mem, mhost.data(), mbytes, hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -169,21 +228,49 @@ int tp_solve(lc_ctx* c, const T* r, T* phi, T* t1, T* t2) {
       return (const T*)a[which];
     }
   };
+  auto half = [](const AxisModes& M, int which) -> const T* {
+    if constexpr (sizeof(T) == sizeof(double))
+      return (const T*)M.h64[which];
+    else
+      return (const T*)M.h32[which];
+  };
+  auto lams = [](const AxisModes& M) { return M.sym ? M.lam_s : M.lam; };
   const AxisModes &X = c->modes[0], &Y = c->modes[1], &Z = c->modes[2];
   hipStream_t s = c->stream;
   const int n_yz = ny * nz, n_xz = nx * nz;
   const double* nul = nullptr;
   // forward: x (contiguous lines), y (columns (k, i), rows nx apart), z (rows nx*ny apart),
-  // the division by lam_x + lam_y + lam_z fused into the z transform
-  KLAUNCH(c, LC_K_TP_X, launch_tp_right<T>(n_yz, nx, nx, r, pick(X, 2), t1, s));
-  KLAUNCH(c, LC_K_TP_Y, launch_tp_left<T>(ny, n_xz, ny, pick(Y, 0), t1, t2, nx, pl, nx, nul, nul, nul, 1, 0, 0, 0, s));
-  KLAUNCH(c, LC_K_TP_Z, launch_tp_left<T>(nz, (int)pl, nz, pick(Z, 0), t2, t1, (int)pl, 0, pl, Z.lam, Y.lam, X.lam,
-                                          nx, c->zero_mode[2], c->zero_mode[1], c->zero_mode[0], s));
+  // the division by lam_x + lam_y + lam_z fused into the z transform; a mirror-symmetric
+  // axis uses the folded half-size transforms (modes parity-sorted)
+  if (X.sym)
+    KLAUNCH(c, LC_K_TP_X, launch_tpf_right<T>(nx, n_yz, r, half(X, 4), half(X, 5), t1, s));
+  else
+    KLAUNCH(c, LC_K_TP_X, launch_tp_right<T>(n_yz, nx, nx, r, pick(X, 2), t1, s));
+  if (Y.sym)
+    KLAUNCH(c, LC_K_TP_Y, launch_tpf_left<T>(ny, n_xz, half(Y, 0), half(Y, 1), t1, t2, nx, pl, nx, nul, nul, nul, 1, 0, 0,
+                                             0, s));
+  else
+    KLAUNCH(c, LC_K_TP_Y, launch_tp_left<T>(ny, n_xz, ny, pick(Y, 0), t1, t2, nx, pl, nx, nul, nul, nul, 1, 0, 0, 0, s));
+  if (Z.sym)
+    KLAUNCH(c, LC_K_TP_Z, launch_tpf_left<T>(nz, (int)pl, half(Z, 0), half(Z, 1), t2, t1, (int)pl, 0, pl, lams(Z),
+                                             lams(Y), lams(X), nx, c->zero_mode[2], c->zero_mode[1], c->zero_mode[0], s));
+  else
+    KLAUNCH(c, LC_K_TP_Z, launch_tp_left<T>(nz, (int)pl, nz, pick(Z, 0), t2, t1, (int)pl, 0, pl, lams(Z), lams(Y),
+                                            lams(X), nx, c->zero_mode[2], c->zero_mode[1], c->zero_mode[0], s));
   // backward: z, y, x
-  KLAUNCH(c, LC_K_TP_Z, launch_tp_left<T>(nz, (int)pl, nz, pick(Z, 1), t1, t2, (int)pl, 0, pl, nul, nul, nul, 1, 0, 0,
-                                          0, s));
-  KLAUNCH(c, LC_K_TP_Y, launch_tp_left<T>(ny, n_xz, ny, pick(Y, 1), t2, t1, nx, pl, nx, nul, nul, nul, 1, 0, 0, 0, s));
-  KLAUNCH(c, LC_K_TP_X, launch_tp_right<T>(n_yz, nx, nx, t1, pick(X, 3), phi, s));
+  if (Z.sym)
+    KLAUNCH(c, LC_K_TP_Z, launch_tpu_left<T>(nz, (int)pl, half(Z, 2), half(Z, 3), t1, t2, (int)pl, 0, pl, s));
+  else
+    KLAUNCH(c, LC_K_TP_Z, launch_tp_left<T>(nz, (int)pl, nz, pick(Z, 1), t1, t2, (int)pl, 0, pl, nul, nul, nul, 1, 0, 0,
+                                            0, s));
+  if (Y.sym)
+    KLAUNCH(c, LC_K_TP_Y, launch_tpu_left<T>(ny, n_xz, half(Y, 2), half(Y, 3), t2, t1, nx, pl, nx, s));
+  else
+    KLAUNCH(c, LC_K_TP_Y, launch_tp_left<T>(ny, n_xz, ny, pick(Y, 1), t2, t1, nx, pl, nx, nul, nul, nul, 1, 0, 0, 0, s));
+  if (X.sym)
+    KLAUNCH(c, LC_K_TP_X, launch_tpu_right<T>(nx, n_yz, t1, half(X, 6), half(X, 7), phi, s));
+  else
+    KLAUNCH(c, LC_K_TP_X, launch_tp_right<T>(n_yz, nx, nx, t1, pick(X, 3), phi, s));
   return LC_OK;
 }
 

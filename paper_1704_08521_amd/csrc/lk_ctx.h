@@ -33,10 +33,19 @@ struct AxisHost {
 };
 
 // Tensor-product factorization of one axis, device copies in float64 and float32.
+// On a mirror-symmetric axis the modes are also stored parity-sorted (he even modes,
+// then ho odd ones) as half-size matrices for the folded transforms.
 struct AxisModes {
   double* lam = nullptr;          // n eigenvalues
   double *F = nullptr, *Bk = nullptr, *FT = nullptr, *BkT = nullptr;
   float *F32 = nullptr, *Bk32 = nullptr, *FT32 = nullptr, *BkT32 = nullptr;
+  bool sym = false;
+  int he = 0, ho = 0;
+  double* lam_s = nullptr;        // eigenvalues in parity-sorted order
+  // [0] Ae (he x he), [1] Ao (ho x ho), [2] Se (he x he), [3] So (he x ho),
+  // [4] FTe (he x he), [5] FTo (ho x ho), [6] SeT (he x he), [7] SoT (ho x he)
+  double* h64[8] = {};
+  float* h32[8] = {};
 };
 
 }  // namespace lk

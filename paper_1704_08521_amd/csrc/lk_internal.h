@@ -101,6 +101,23 @@ hipError_t launch_tp_left(int M, int N, int K, const T* A, const T* B, T* C, int
 template <typename T>
 hipError_t launch_tp_right(int M, int N, int K, const T* A, const T* B, T* C, hipStream_t st);
 
+// Mirror-symmetric axes (parity-sorted modes, he = ceil(n/2) even, ho = floor(n/2) odd):
+// forward transforms fold line values on load and use the half matrices Ae (he x he) /
+// Ao (ho x ho) (left) or their transposes Be / Bo (right); backward transforms use
+// Se (he x he), So (he x ho) (left) or SeT (he x he), SoT (ho x he) (right) and unfold.
+// Layout and scaling arguments as launch_tp_left / launch_tp_right.
+template <typename T>
+hipError_t launch_tpf_left(int n, int N, const T* Ae, const T* Ao, const T* B, T* C, int nseg, long seg_stride,
+                           long kstride, const double* lm, const double* ly, const double* lx, int nxs, int zm, int zj,
+                           int zi, hipStream_t st);
+template <typename T>
+hipError_t launch_tpu_left(int n, int N, const T* Se, const T* So, const T* B, T* C, int nseg, long seg_stride,
+                           long kstride, hipStream_t st);
+template <typename T>
+hipError_t launch_tpf_right(int n, int Mlines, const T* A, const T* Be, const T* Bo, T* C, hipStream_t st);
+template <typename T>
+hipError_t launch_tpu_right(int n, int Mlines, const T* A, const T* SeT, const T* SoT, T* C, hipStream_t st);
+
 // Precision casts.
 hipError_t launch_d2f(size_t n, const double* in, float* out, hipStream_t st);
 // out = in (float -> double), or out += in when accumulate

@@ -279,4 +279,69 @@ bool neumann_modes(int n, const double* d, const double* dd, std::vector<double>
   return true;
 }
 
+// Modes of a mirror-symmetric axis (d[i] = d[n-1-i], dd[f] = dd[n-f]) restricted to the
+// even or odd subspace.  Basis: e_p = (delta_p + delta_{n-1-p}) / sqrt2 (p < n/2) plus
+// delta_mid for odd n (even), o_p = (delta_p - delta_{n-1-p}) / sqrt2 (odd).  The
+// projected K and M are tridiagonal and diagonal, so the half problem is solved like
+// the full one; its eigenvectors are exactly even / odd, which separates the nearly
+// degenerate mirror pairs that wall-refined grids produce.  Outputs: lam (h ascending),
+// Sh (h x h, row-major [p][k]): the k-th mode in the basis, Sh^T Mh Sh = I.
+bool neumann_half_modes(int n, const double* d, const double* dd, bool odd, std::vector<double>& lam,
+                        std::vector<double>& Sh) {
+  const int he = (n + 1) / 2, ho = n / 2;
+  const int h = odd ? ho : he;
+  if (h == 0) {
+    lam.clear();
+    Sh.clear();
+    return true;
+  }
+  const double r2 = std::sqrt(0.5);
+  // full operator entries: K[i][i] = -(c_i + c_{i+1}), K[i][i+1] = c_{i+1}, c_f = 1/dd[f], walls 0
+  auto K = [&](int i, int j) -> double {
+    if (j == i) {
+      double v = 0.0;
+      if (i > 0) v -= 1.0 / dd[i];
+      if (i < n - 1) v -= 1.0 / dd[i + 1];
+      return v;
+    }
+    if (j == i + 1) return 1.0 / dd[i + 1];
+    if (j == i - 1) return 1.0 / dd[i];
+    return 0.0;
+  };
+  // basis column p: up to two (index, weight) entries
+  auto col = [&](int p, int* idx, double* w) -> int {
+    if (!odd && (n % 2 == 1) && p == he - 1) {
+      idx[0] = p;
+      w[0] = 1.0;
+      return 1;
+    }
+    idx[0] = p;
+    w[0] = r2;
+    idx[1] = n - 1 - p;
+    w[1] = odd ? -r2 : r2;
+    return 2;
+  };
+  auto proj = [&](int p, int q) -> double {
+    int ip[2], iq[2];
+    double wp[2], wq[2];
+    const int np = col(p, ip, wp), nq = col(q, iq, wq);
+    double v = 0.0;
+    for (int a = 0; a < np; ++a)
+      for (int b = 0; b < nq; ++b) v += wp[a] * wq[b] * K(ip[a], iq[b]);
+    return v;
+  };
+  std::vector<double> m(h), a(h), b(std::max(h - 1, 1), 0.0);
+  for (int p = 0; p < h; ++p) m[p] = d[p];  // e_p^T M e_p = (d_p + d_{n-1-p}) / 2 = d_p
+  for (int p = 0; p < h; ++p) a[p] = proj(p, p) / m[p];
+  for (int p = 0; p + 1 < h; ++p) b[p] = proj(p, p + 1) / std::sqrt(m[p] * m[p + 1]);
+  std::vector<double> Q;
+  if (!sym_tridiag_eig(h, a, b, lam, Q)) return false;
+  Sh.resize((size_t)h * h);
+  for (int p = 0; p < h; ++p) {
+    const double sq = std::sqrt(m[p]);
+    for (int k = 0; k < h; ++k) Sh[(size_t)p * h + k] = Q[(size_t)p * h + k] / sq;
+  }
+  return true;
+}
+
 }  // namespace lk

@@ -33,6 +33,10 @@ bool sym_tridiag_eig(int n, std::vector<double> a, std::vector<double> b, std::v
 // Modes of the 1D Neumann operator A = M^-1 K of one axis (M = diag(d), K the
 // couplings 1/dd across interior faces): K s = lam M s.  S (row-major, columns
 // s_m, S^T M S = I) and Wf = S^T M (row-major).  lam ascending (last ~ 0).
+// Even (odd = false) or odd modes of a mirror-symmetric axis in the half basis; see
+// lk_linalg.cpp.
+bool neumann_half_modes(int n, const double* d, const double* dd, bool odd, std::vector<double>& lam,
+                        std::vector<double>& Sh);
 bool neumann_modes(int n, const double* d, const double* dd, std::vector<double>& lam, std::vector<double>& S,
                    std::vector<double>& Wf);
 

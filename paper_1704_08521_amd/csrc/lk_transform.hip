@@ -193,6 +193,400 @@ __global__ void __launch_bounds__(TPR* TPC) k_tp_right(int M, int N, int K, cons
   }
 }
 
+// ------------------------------------------------ mirror-symmetric axes
+// On a grid symmetric under i -> n-1-i every mode of an axis is even or odd, so a
+// transform splits into two half-size ones.  Modes are stored parity-sorted (he even
+// modes, then ho odd ones; he = ceil(n/2), ho = floor(n/2)).  Forward: line values are
+// folded on load, f_i + f_{n-1-i} (even; the middle value alone when n is odd) and
+// f_i - f_{n-1-i} (odd), and contracted with the even (he x he) or odd (ho x ho) half
+// matrix; blocks with blockIdx.y (left) / blockIdx.x (right) below nbe do the even
+// half.  Backward: a_i = sum_e Se[i][e] c_e and b_i = sum_o So[i][o] c_o for i < he,
+// written as phi_i = a_i + b_i and phi_{n-1-i} = a_i - b_i.
+
+// Left, forward: C[r][col] (r parity-sorted mode) = sum_k Ah[r'][k] fold(B)[k][col];
+// B and C have the segmented-column layout of k_tp_left; optional eigenvalue scaling.
+template <typename T, int TM, int TN, int TBK>
+__global__ void __launch_bounds__(TPR* TPC) k_tpf_left(int n, int he, int ho, int nbe, int N, const T* __restrict__ Ae,
+                                                       const T* __restrict__ Ao, const T* __restrict__ B,
+                                                       T* __restrict__ C, int nseg, long seg_stride, long kstride,
+                                                       const double* __restrict__ lm, const double* __restrict__ ly,
+                                                       const double* __restrict__ lx, int nxs, int zm, int zj, int zi) {
+  constexpr int BM = TPR * TM, BN = TPC * TN;
+  __shared__ T As[TBK][BM + 1];
+  __shared__ T Bs[TBK][BN];
+  const bool odd = (int)blockIdx.y >= nbe;
+  const int M = odd ? ho : he, K = M;
+  const T* A = odd ? Ao : Ae;
+  const T sgn = odd ? T(-1) : T(1);
+  const int rowoff = odd ? he : 0;
+  const int tid = threadIdx.x;
+  const int tx = tid % TPC, ty = tid / TPC;
+  const int m0 = (odd ? (int)blockIdx.y - nbe : (int)blockIdx.y) * BM, n0 = blockIdx.x * BN;
+  const int lcol = tid % BN, lrow = tid / BN;
+  constexpr int LROWS = (TPR * TPC) / BN;
+  const int gnl = n0 + lcol;
+  const long boff = (gnl < N) ? (long)(gnl / nseg) * seg_stride + (gnl % nseg) : 0;
+  T acc[TM][TN];
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int c = 0; c < TN; ++c) acc[a][c] = T(0);
+  constexpr int NTH = TPR * TPC;
+  constexpr int NA = (BM * TBK + NTH - 1) / NTH;
+  constexpr int NB = (TBK * BN) / NTH;
+  T ra[NA], rb[NB];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      const int e = tid + q * NTH;
+      const int mm = e / TBK, kk = e % TBK;
+      const int gm = m0 + mm, gk = k0 + kk;
+      const bool ok = e < BM * TBK && gm < M && gk < K;
+      const T x = A[ok ? (long)gm * K + gk : 0];
+      ra[q] = ok ? x : T(0);
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int gk = k0 + lrow + q * LROWS;
+      const bool ok = gnl < N && gk < K;
+      const int gm = n - 1 - gk;
+      const T x1 = B[ok ? boff + (long)gk * kstride : 0];
+      const T x2 = B[ok ? boff + (long)gm * kstride : 0];
+      rb[q] = ok ? (gm == gk ? x1 : x1 + sgn * x2) : T(0);
+    }
+  };
+  auto sstore = [&]() {
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      const int e = tid + q * NTH;
+      if (e < BM * TBK) As[e % TBK][e / TBK] = ra[q];
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) Bs[lrow + q * LROWS][lcol] = rb[q];
+  };
+  gload(0);
+  for (int k0 = 0; k0 < K; k0 += TBK) {
+    sstore();
+    __syncthreads();
+    if (k0 + TBK < K) gload(k0 + TBK);
+#pragma unroll 4
+    for (int kk = 0; kk < TBK; ++kk) {
+      T av[TM], bv[TN];
+#pragma unroll
+      for (int a = 0; a < TM; ++a) av[a] = As[kk][ty + TPR * a];
+#pragma unroll
+      for (int c = 0; c < TN; ++c) bv[c] = Bs[kk][tx + TPC * c];
+#pragma unroll
+      for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int c = 0; c < TN; ++c) acc[a][c] = fma(av[a], bv[c], acc[a][c]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int c = 0; c < TN; ++c) {
+    const int gn = n0 + tx + TPC * c;
+    if (gn >= N) continue;
+    const long off = (long)(gn / nseg) * seg_stride + (gn % nseg);
+    const int jj = lm ? gn / nxs : 0, ii = lm ? gn % nxs : 0;
+    const double sxy = lm ? ly[jj] + lx[ii] : 0.0;
+#pragma unroll
+    for (int a = 0; a < TM; ++a) {
+      const int lr = m0 + ty + TPR * a;
+      if (lr >= M) continue;
+      const int gm = rowoff + lr;
+      T val = acc[a][c];
+      if (lm) val = (gm == zm && jj == zj && ii == zi) ? T(0) : (T)((double)val / (lm[gm] + sxy));
+      C[off + (long)gm * kstride] = val;
+    }
+  }
+}
+
+// Left, backward: rows i < he of a = Se c_e (Se: he x he) and b = So c_o (So: he x ho),
+// C[i] = a + b and C[n-1-i] = a - b; B (parity-sorted modes) and C have the
+// segmented-column layout.
+template <typename T, int TM, int TN, int TBK>
+__global__ void __launch_bounds__(TPR* TPC) k_tpu_left(int n, int he, int ho, int N, const T* __restrict__ Se,
+                                                       const T* __restrict__ So, const T* __restrict__ B,
+                                                       T* __restrict__ C, int nseg, long seg_stride, long kstride) {
+  constexpr int BM = TPR * TM, BN = TPC * TN;
+  __shared__ T As[TBK][BM + 1];
+  __shared__ T Bs[TBK][BN];
+  const int tid = threadIdx.x;
+  const int tx = tid % TPC, ty = tid / TPC;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int lcol = tid % BN, lrow = tid / BN;
+  constexpr int LROWS = (TPR * TPC) / BN;
+  const int gnl = n0 + lcol;
+  const long boff = (gnl < N) ? (long)(gnl / nseg) * seg_stride + (gnl % nseg) : 0;
+  T acc[2][TM][TN];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+      for (int c = 0; c < TN; ++c) acc[h][a][c] = T(0);
+  constexpr int NTH = TPR * TPC;
+  constexpr int NA = (BM * TBK + NTH - 1) / NTH;
+  constexpr int NB = (TBK * BN) / NTH;
+  T ra[NA], rb[NB];
+  // phase 0: even modes (K = he, rows 0..he-1 of B); phase 1: odd modes (K = ho, rows he..)
+  auto gload = [&](int ph, int k0) {
+    const T* A = ph ? So : Se;
+    const int K = ph ? ho : he;
+    const int kb = ph ? he : 0;
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      const int e = tid + q * NTH;
+      const int mm = e / TBK, kk = e % TBK;
+      const int gm = m0 + mm, gk = k0 + kk;
+      const bool ok = e < BM * TBK && gm < he && gk < K;
+      const T x = A[ok ? (long)gm * K + gk : 0];
+      ra[q] = ok ? x : T(0);
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int gk = k0 + lrow + q * LROWS;
+      const bool ok = gnl < N && gk < K;
+      const T x = B[ok ? boff + (long)(kb + gk) * kstride : 0];
+      rb[q] = ok ? x : T(0);
+    }
+  };
+  auto sstore = [&]() {
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      const int e = tid + q * NTH;
+      if (e < BM * TBK) As[e % TBK][e / TBK] = ra[q];
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) Bs[lrow + q * LROWS][lcol] = rb[q];
+  };
+#pragma unroll
+  for (int ph = 0; ph < 2; ++ph) {
+    const int K = ph ? ho : he;
+    gload(ph, 0);
+    for (int k0 = 0; k0 < K; k0 += TBK) {
+      sstore();
+      __syncthreads();
+      if (k0 + TBK < K) gload(ph, k0 + TBK);
+#pragma unroll 4
+      for (int kk = 0; kk < TBK; ++kk) {
+        T av[TM], bv[TN];
+#pragma unroll
+        for (int a = 0; a < TM; ++a) av[a] = As[kk][ty + TPR * a];
+#pragma unroll
+        for (int c = 0; c < TN; ++c) bv[c] = Bs[kk][tx + TPC * c];
+#pragma unroll
+        for (int a = 0; a < TM; ++a)
+#pragma unroll
+          for (int c = 0; c < TN; ++c) acc[ph][a][c] = fma(av[a], bv[c], acc[ph][a][c]);
+      }
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < TN; ++c) {
+    const int gn = n0 + tx + TPC * c;
+    if (gn >= N) continue;
+    const long off = (long)(gn / nseg) * seg_stride + (gn % nseg);
+#pragma unroll
+    for (int a = 0; a < TM; ++a) {
+      const int i = m0 + ty + TPR * a;
+      if (i >= he) continue;
+      const T va = acc[0][a][c], vb = acc[1][a][c];
+      C[off + (long)i * kstride] = va + vb;
+      if (i < ho) C[off + (long)(n - 1 - i) * kstride] = va - vb;
+    }
+  }
+}
+
+// Right, forward: C[line][r] (parity-sorted mode) = sum_k fold(A)[line][k] Bh[k][r'];
+// A: lines of n contiguous values; Bh: FTe (he x he) or FTo (ho x ho); C: lines of n.
+template <typename T, int TM, int TN, int TBK>
+__global__ void __launch_bounds__(TPR* TPC) k_tpf_right(int n, int he, int ho, int nbe, int Mlines,
+                                                        const T* __restrict__ A, const T* __restrict__ Be,
+                                                        const T* __restrict__ Bo, T* __restrict__ C) {
+  constexpr int BM = TPR * TM, BN = TPC * TN;
+  __shared__ T As[TBK][BM + 1];
+  __shared__ T Bs[TBK][BN];
+  const bool odd = (int)blockIdx.x >= nbe;
+  const int N = odd ? ho : he, K = N;
+  const T* B = odd ? Bo : Be;
+  const T sgn = odd ? T(-1) : T(1);
+  const int coloff = odd ? he : 0;
+  const int tid = threadIdx.x;
+  const int tx = tid % TPC, ty = tid / TPC;
+  const int m0 = blockIdx.y * BM, n0 = (odd ? (int)blockIdx.x - nbe : (int)blockIdx.x) * BN;
+  T acc[TM][TN];
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int c = 0; c < TN; ++c) acc[a][c] = T(0);
+  constexpr int NTH = TPR * TPC;
+  constexpr int NA = (BM * TBK) / NTH;
+  constexpr int NB = (TBK * BN + NTH - 1) / NTH;
+  T ra[NA], rb[NB];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      const int e = tid + q * NTH;
+      const int mm = e / TBK, kk = e % TBK;
+      const int gm = m0 + mm, gk = k0 + kk;
+      const bool ok = gm < Mlines && gk < K;
+      const int gr = n - 1 - gk;
+      const T x1 = A[ok ? (long)gm * n + gk : 0];
+      const T x2 = A[ok ? (long)gm * n + gr : 0];
+      ra[q] = ok ? (gr == gk ? x1 : x1 + sgn * x2) : T(0);
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int e = tid + q * NTH;
+      const int kk = e / BN, nn = e % BN;
+      const int gk = k0 + kk, gn = n0 + nn;
+      const bool ok = e < TBK * BN && gk < K && gn < N;
+      const T x = B[ok ? (long)gk * N + gn : 0];
+      rb[q] = ok ? x : T(0);
+    }
+  };
+  auto sstore = [&]() {
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      const int e = tid + q * NTH;
+      As[e % TBK][e / TBK] = ra[q];
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int e = tid + q * NTH;
+      if (e < TBK * BN) Bs[e / BN][e % BN] = rb[q];
+    }
+  };
+  gload(0);
+  for (int k0 = 0; k0 < K; k0 += TBK) {
+    sstore();
+    __syncthreads();
+    if (k0 + TBK < K) gload(k0 + TBK);
+#pragma unroll 4
+    for (int kk = 0; kk < TBK; ++kk) {
+      T av[TM], bv[TN];
+#pragma unroll
+      for (int a = 0; a < TM; ++a) av[a] = As[kk][ty + TPR * a];
+#pragma unroll
+      for (int c = 0; c < TN; ++c) bv[c] = Bs[kk][tx + TPC * c];
+#pragma unroll
+      for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int c = 0; c < TN; ++c) acc[a][c] = fma(av[a], bv[c], acc[a][c]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < TM; ++a) {
+    const int gm = m0 + ty + TPR * a;
+    if (gm >= Mlines) continue;
+#pragma unroll
+    for (int c = 0; c < TN; ++c) {
+      const int gn = n0 + tx + TPC * c;
+      if (gn < N) C[(long)gm * n + coloff + gn] = acc[a][c];
+    }
+  }
+}
+
+// Right, backward: for each line, a_i = sum_e c_e SeT[e][i], b_i = sum_o c_o SoT[o][i]
+// (i < he; SeT: he x he, SoT: ho x he), C[line][i] = a + b, C[line][n-1-i] = a - b.
+template <typename T, int TM, int TN, int TBK>
+__global__ void __launch_bounds__(TPR* TPC) k_tpu_right(int n, int he, int ho, int Mlines, const T* __restrict__ A,
+                                                        const T* __restrict__ SeT, const T* __restrict__ SoT,
+                                                        T* __restrict__ C) {
+  constexpr int BM = TPR * TM, BN = TPC * TN;
+  __shared__ T As[TBK][BM + 1];
+  __shared__ T Bs[TBK][BN];
+  const int tid = threadIdx.x;
+  const int tx = tid % TPC, ty = tid / TPC;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  T acc[2][TM][TN];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+      for (int c = 0; c < TN; ++c) acc[h][a][c] = T(0);
+  constexpr int NTH = TPR * TPC;
+  constexpr int NA = (BM * TBK) / NTH;
+  constexpr int NB = (TBK * BN + NTH - 1) / NTH;
+  T ra[NA], rb[NB];
+  auto gload = [&](int ph, int k0) {
+    const T* B = ph ? SoT : SeT;
+    const int K = ph ? ho : he;
+    const int kb = ph ? he : 0;
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      const int e = tid + q * NTH;
+      const int mm = e / TBK, kk = e % TBK;
+      const int gm = m0 + mm, gk = k0 + kk;
+      const bool ok = gm < Mlines && gk < K;
+      const T x = A[ok ? (long)gm * n + kb + gk : 0];
+      ra[q] = ok ? x : T(0);
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int e = tid + q * NTH;
+      const int kk = e / BN, nn = e % BN;
+      const int gk = k0 + kk, gn = n0 + nn;
+      const bool ok = e < TBK * BN && gk < K && gn < he;
+      const T x = B[ok ? (long)gk * he + gn : 0];
+      rb[q] = ok ? x : T(0);
+    }
+  };
+  auto sstore = [&]() {
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      const int e = tid + q * NTH;
+      As[e % TBK][e / TBK] = ra[q];
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int e = tid + q * NTH;
+      if (e < TBK * BN) Bs[e / BN][e % BN] = rb[q];
+    }
+  };
+#pragma unroll
+  for (int ph = 0; ph < 2; ++ph) {
+    const int K = ph ? ho : he;
+    gload(ph, 0);
+    for (int k0 = 0; k0 < K; k0 += TBK) {
+      sstore();
+      __syncthreads();
+      if (k0 + TBK < K) gload(ph, k0 + TBK);
+#pragma unroll 4
+      for (int kk = 0; kk < TBK; ++kk) {
+        T av[TM], bv[TN];
+#pragma unroll
+        for (int a = 0; a < TM; ++a) av[a] = As[kk][ty + TPR * a];
+#pragma unroll
+        for (int c = 0; c < TN; ++c) bv[c] = Bs[kk][tx + TPC * c];
+#pragma unroll
+        for (int a = 0; a < TM; ++a)
+#pragma unroll
+          for (int c = 0; c < TN; ++c) acc[ph][a][c] = fma(av[a], bv[c], acc[ph][a][c]);
+      }
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < TM; ++a) {
+    const int gm = m0 + ty + TPR * a;
+    if (gm >= Mlines) continue;
+#pragma unroll
+    for (int c = 0; c < TN; ++c) {
+      const int i = n0 + tx + TPC * c;
+      if (i >= he) continue;
+      const T va = acc[0][a][c], vb = acc[1][a][c];
+      C[(long)gm * n + i] = va + vb;
+      if (i < ho) C[(long)gm * n + (n - 1 - i)] = va - vb;
+    }
+  }
+}
+
 // Register tile along the transformed dimension: the smallest that covers n with 16
 // threads, except that 161..224 uses 7 (two blocks of 112), which measured faster at
 // n = 200 than one block of 13 (n > 256 uses several blocks).
@@ -254,6 +648,107 @@ hipError_t launch_tp_right(int M, int N, int K, const T* A, const T* B, T* C, hi
   }
 }
 
+// Tile along a half (he <= 112 in one block, larger halves in several).
+inline int pick_half_tile(int h) {
+  const int need = (h + 15) / 16;
+  const int opts[] = {1, 2, 4, 7, 8, 10, 13, 16};
+  for (int t : opts)
+    if (t >= need) return t;
+  return 16;
+}
+
+template <typename T>
+hipError_t launch_tpf_left(int n, int N, const T* Ae, const T* Ao, const T* B, T* C, int nseg, long seg_stride,
+                           long kstride, const double* lm, const double* ly, const double* lx, int nxs, int zm, int zj,
+                           int zi, hipStream_t st) {
+  const int he = (n + 1) / 2, ho = n / 2;
+#define TPF(TM)                                                                                               \
+  {                                                                                                           \
+    const int nbe = (int)blocks_for(he, TPR * TM), nbo = (int)blocks_for(ho > 0 ? ho : 1, TPR * TM);        \
+    hipLaunchKernelGGL((k_tpf_left<T, TM, 4, 16>), dim3(blocks_for(N, TPC * 4), nbe + nbo), dim3(TPR * TPC), 0, \
+                       st, n, he, ho, nbe, N, Ae, Ao, B, C, nseg, seg_stride, kstride, lm, ly, lx, nxs, zm, zj, zi); \
+    break;                                                                                                    \
+  }
+  switch (pick_half_tile(he)) {
+    case 1: TPF(1)
+    case 2: TPF(2)
+    case 4: TPF(4)
+    case 7: TPF(7)
+    case 8: TPF(8)
+    case 10: TPF(10)
+    case 13: TPF(13)
+    default: TPF(16)
+  }
+#undef TPF
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_tpu_left(int n, int N, const T* Se, const T* So, const T* B, T* C, int nseg, long seg_stride,
+                           long kstride, hipStream_t st) {
+  const int he = (n + 1) / 2, ho = n / 2;
+  // two row blocks per half at n = 200 (the grid would otherwise hold only one block per column tile)
+#define TPU(TM)                                                                                                  \
+  {                                                                                                              \
+    hipLaunchKernelGGL((k_tpu_left<T, TM, 4, 16>), dim3(blocks_for(N, TPC * 4), blocks_for(he, TPR * TM)),      \
+                       dim3(TPR * TPC), 0, st, n, he, ho, N, Se, So, B, C, nseg, seg_stride, kstride);          \
+    break;                                                                                                       \
+  }
+  switch (pick_half_tile((he + 1) / 2)) {
+    case 1: TPU(1)
+    case 2: TPU(2)
+    case 4: TPU(4)
+    case 7: TPU(7)
+    default: TPU(8)
+  }
+#undef TPU
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_tpf_right(int n, int Mlines, const T* A, const T* Be, const T* Bo, T* C, hipStream_t st) {
+  const int he = (n + 1) / 2, ho = n / 2;
+#define TPFR(TN)                                                                                               \
+  {                                                                                                            \
+    const int nbe = (int)blocks_for(he, TPC * TN), nbo = (int)blocks_for(ho > 0 ? ho : 1, TPC * TN);         \
+    hipLaunchKernelGGL((k_tpf_right<T, 4, TN, 16>), dim3(nbe + nbo, blocks_for(Mlines, TPR * 4)),             \
+                       dim3(TPR * TPC), 0, st, n, he, ho, nbe, Mlines, A, Be, Bo, C);                          \
+    break;                                                                                                     \
+  }
+  switch (pick_half_tile(he)) {
+    case 1: TPFR(1)
+    case 2: TPFR(2)
+    case 4: TPFR(4)
+    case 7: TPFR(7)
+    case 8: TPFR(8)
+    case 10: TPFR(10)
+    case 13: TPFR(13)
+    default: TPFR(16)
+  }
+#undef TPFR
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_tpu_right(int n, int Mlines, const T* A, const T* SeT, const T* SoT, T* C, hipStream_t st) {
+  const int he = (n + 1) / 2, ho = n / 2;
+#define TPUR(TN)                                                                                               \
+  {                                                                                                            \
+    hipLaunchKernelGGL((k_tpu_right<T, 4, TN, 16>), dim3(blocks_for(he, TPC * TN), blocks_for(Mlines, TPR * 4)), \
+                       dim3(TPR * TPC), 0, st, n, he, ho, Mlines, A, SeT, SoT, C);                            \
+    break;                                                                                                     \
+  }
+  switch (pick_half_tile((he + 1) / 2)) {
+    case 1: TPUR(1)
+    case 2: TPUR(2)
+    case 4: TPUR(4)
+    case 7: TPUR(7)
+    default: TPUR(8)
+  }
+#undef TPUR
+  return hipGetLastError();
+}
+
 template hipError_t launch_tp_left<double>(int, int, int, const double*, const double*, double*, int, long, long,
                                            const double*, const double*, const double*, int, int, int, int,
                                            hipStream_t);
@@ -262,5 +757,15 @@ template hipError_t launch_tp_left<float>(int, int, int, const float*, const flo
                                           hipStream_t);
 template hipError_t launch_tp_right<double>(int, int, int, const double*, const double*, double*, hipStream_t);
 template hipError_t launch_tp_right<float>(int, int, int, const float*, const float*, float*, hipStream_t);
+
+#define LK_TPF_INST(T)                                                                                           \
+  template hipError_t launch_tpf_left<T>(int, int, const T*, const T*, const T*, T*, int, long, long, const double*, \
+                                         const double*, const double*, int, int, int, int, hipStream_t);          \
+  template hipError_t launch_tpu_left<T>(int, int, const T*, const T*, const T*, T*, int, long, long, hipStream_t); \
+  template hipError_t launch_tpf_right<T>(int, int, const T*, const T*, const T*, T*, hipStream_t);                \
+  template hipError_t launch_tpu_right<T>(int, int, const T*, const T*, const T*, T*, hipStream_t);
+LK_TPF_INST(double)
+LK_TPF_INST(float)
+#undef LK_TPF_INST
 
 }  // namespace lk

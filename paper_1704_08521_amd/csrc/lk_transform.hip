@@ -648,6 +648,10 @@ hipError_t launch_tp_right(int M, int N, int K, const T* A, const T* B, T* C, hi
   }
 }
 
+// Contraction chunk for a half of length k: 20 when it pads less than 16 (k = 100 at
+// n = 200 measured 5-10% faster), else 16.
+inline bool chunk20(int k) { return (k + 19) / 20 * 20 - k < (k + 15) / 16 * 16 - k; }
+
 // Tile along a half (he <= 112 in one block, larger halves in several).
 inline int pick_half_tile(int h) {
   const int need = (h + 15) / 16;
@@ -662,12 +666,17 @@ hipError_t launch_tpf_left(int n, int N, const T* Ae, const T* Ao, const T* B, T
                            long kstride, const double* lm, const double* ly, const double* lx, int nxs, int zm, int zj,
                            int zi, hipStream_t st) {
   const int he = (n + 1) / 2, ho = n / 2;
-#define TPF(TM)                                                                                               \
-  {                                                                                                           \
-    const int nbe = (int)blocks_for(he, TPR * TM), nbo = (int)blocks_for(ho > 0 ? ho : 1, TPR * TM);        \
-    hipLaunchKernelGGL((k_tpf_left<T, TM, 4, 16>), dim3(blocks_for(N, TPC * 4), nbe + nbo), dim3(TPR * TPC), 0, \
-                       st, n, he, ho, nbe, N, Ae, Ao, B, C, nseg, seg_stride, kstride, lm, ly, lx, nxs, zm, zj, zi); \
-    break;                                                                                                    \
+#define TPF(TM)                                                                                                  \
+  {                                                                                                              \
+    const int nbe = (int)blocks_for(he, TPR * TM), nbo = (int)blocks_for(ho > 0 ? ho : 1, TPR * TM);           \
+    const dim3 grid(blocks_for(N, TPC * 4), nbe + nbo);                                                          \
+    if (chunk20(he))                                                                                             \
+      hipLaunchKernelGGL((k_tpf_left<T, TM, 4, 20>), grid, dim3(TPR * TPC), 0, st, n, he, ho, nbe, N, Ae, Ao, B, C, \
+                         nseg, seg_stride, kstride, lm, ly, lx, nxs, zm, zj, zi);                                \
+    else                                                                                                         \
+      hipLaunchKernelGGL((k_tpf_left<T, TM, 4, 16>), grid, dim3(TPR * TPC), 0, st, n, he, ho, nbe, N, Ae, Ao, B, C, \
+                         nseg, seg_stride, kstride, lm, ly, lx, nxs, zm, zj, zi);                                \
+    break;                                                                                                       \
   }
   switch (pick_half_tile(he)) {
     case 1: TPF(1)
@@ -690,8 +699,13 @@ hipError_t launch_tpu_left(int n, int N, const T* Se, const T* So, const T* B, T
   // two row blocks per half at n = 200 (the grid would otherwise hold only one block per column tile)
 #define TPU(TM)                                                                                                  \
   {                                                                                                              \
-    hipLaunchKernelGGL((k_tpu_left<T, TM, 4, 16>), dim3(blocks_for(N, TPC * 4), blocks_for(he, TPR * TM)),      \
-                       dim3(TPR * TPC), 0, st, n, he, ho, N, Se, So, B, C, nseg, seg_stride, kstride);          \
+    const dim3 grid(blocks_for(N, TPC * 4), blocks_for(he, TPR * TM));                                           \
+    if (chunk20(he))                                                                                             \
+      hipLaunchKernelGGL((k_tpu_left<T, TM, 4, 20>), grid, dim3(TPR * TPC), 0, st, n, he, ho, N, Se, So, B, C, nseg, \
+                         seg_stride, kstride);                                                                   \
+    else                                                                                                         \
+      hipLaunchKernelGGL((k_tpu_left<T, TM, 4, 16>), grid, dim3(TPR * TPC), 0, st, n, he, ho, N, Se, So, B, C, nseg, \
+                         seg_stride, kstride);                                                                   \
     break;                                                                                                       \
   }
   switch (pick_half_tile((he + 1) / 2)) {
@@ -734,8 +748,11 @@ hipError_t launch_tpu_right(int n, int Mlines, const T* A, const T* SeT, const T
   const int he = (n + 1) / 2, ho = n / 2;
 #define TPUR(TN)                                                                                               \
   {                                                                                                            \
-    hipLaunchKernelGGL((k_tpu_right<T, 4, TN, 16>), dim3(blocks_for(he, TPC * TN), blocks_for(Mlines, TPR * 4)), \
-                       dim3(TPR * TPC), 0, st, n, he, ho, Mlines, A, SeT, SoT, C);                            \
+    const dim3 grid(blocks_for(he, TPC * TN), blocks_for(Mlines, TPR * 4));                                    \
+    if (chunk20(he))                                                                                           \
+      hipLaunchKernelGGL((k_tpu_right<T, 4, TN, 20>), grid, dim3(TPR * TPC), 0, st, n, he, ho, Mlines, A, SeT, SoT, C); \
+    else                                                                                                       \
+      hipLaunchKernelGGL((k_tpu_right<T, 4, TN, 16>), grid, dim3(TPR * TPC), 0, st, n, he, ho, Mlines, A, SeT, SoT, C); \
     break;                                                                                                     \
   }
   switch (pick_half_tile((he + 1) / 2)) {

@@ -303,67 +303,88 @@ __global__ void __launch_bounds__(TX* TY) k_momentum(GridDev g, const double* __
 }
 
 // ---------------------------------------------------------------- divergence
-__global__ void __launch_bounds__(kReduceBlock) k_divergence(GridDev g, Vel V, double* __restrict__ r,
-                                                             double* __restrict__ partials) {
+// One thread per (i, j) column of cells marching over KZ planes, so the w face
+// between two cells is read once (carried in a register); tiles are grouped per XCD.
+constexpr int kDivTX = 64, kDivTY = 4, kDivKZ = 4;
+
+template <int KZ>
+__global__ void __launch_bounds__(kDivTX* kDivTY) k_divergence(GridDev g, Vel V, double* __restrict__ r,
+                                                               double* __restrict__ partials, int nbx, int nby) {
   const int nx = g.x.n, ny = g.y.n, nz = g.z.n;
-  const size_t ncell = (size_t)nx * ny * nz;
-  const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = xcd_tile(blockIdx.x, gridDim.x);
+  const int i = (t % nbx) * kDivTX + (int)(threadIdx.x % kDivTX);
+  const int j = ((t / nbx) % nby) * kDivTY + (int)(threadIdx.x / kDivTX);
+  const int k0 = (t / (nbx * nby)) * KZ, k1 = min(k0 + KZ, nz);
   double contrib = 0.0;
-  if (c < ncell) {
-    const int i = (int)(c % nx);
-    const int j = (int)((c / nx) % ny);
-    const int k = (int)(c / ((size_t)nx * ny));
-    const double dv = (V.U(k, j, i + 1) - V.U(k, j, i)) * g.x.rd[i] +
-                      (V.V(k, j + 1, i) - V.V(k, j, i)) * g.y.rd[j] +
-                      (V.W(k + 1, j, i) - V.W(k, j, i)) * g.z.rd[k];
-    if (r) r[c] = dv;
-    contrib = g.x.d[i] * g.y.d[j] * g.z.d[k] * dv * dv;
+  if (i < nx && j < ny) {
+    const double rdx = g.x.rd[i], rdy = g.y.rd[j], dxy = g.x.d[i] * g.y.d[j];
+    double wlo = V.W(k0, j, i);
+    for (int k = k0; k < k1; ++k) {
+      const double whi = V.W(k + 1, j, i);
+      const double dv = (V.U(k, j, i + 1) - V.U(k, j, i)) * rdx + (V.V(k, j + 1, i) - V.V(k, j, i)) * rdy +
+                        (whi - wlo) * g.z.rd[k];
+      if (r) r[((size_t)k * ny + j) * nx + i] = dv;
+      contrib += dxy * g.z.d[k] * dv * dv;
+      wlo = whi;
+    }
   }
   if (partials) {
-    const double t = block_sum(contrib);
-    if (threadIdx.x == 0) partials[blockIdx.x] = t;
+    const double s = block_sum(contrib);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
   }
 }
 
 // ---------------------------------------------------------------- correction
-__global__ void __launch_bounds__(256) k_correct(GridDev g, const double* __restrict__ w,
-                                                 const double* __restrict__ phi, double* __restrict__ v,
-                                                 double* __restrict__ p, int accumulate) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y * blockDim.y + threadIdx.y;
-  const int k = blockIdx.z;
+// One thread per (i, j) face column marching over KZ planes (phi of the plane
+// below carried in a register); tiles grouped per XCD.
+constexpr int kCorTX = 64, kCorTY = 4, kCorKZ = 2;
+
+template <int KZ>
+__global__ void __launch_bounds__(kCorTX* kCorTY) k_correct(GridDev g, const double* __restrict__ w,
+                                                            const double* __restrict__ phi, double* __restrict__ v,
+                                                            double* __restrict__ p, int accumulate, int nbx, int nby) {
   const int nx = g.x.n, ny = g.y.n, nz = g.z.n;
-  if (i > nx || j > ny || k > nz) return;
+  const int t = xcd_tile(blockIdx.x, gridDim.x);
+  const int i = (t % nbx) * kCorTX + (int)(threadIdx.x % kCorTX);
+  const int j = ((t / nbx) % nby) * kCorTY + (int)(threadIdx.x / kCorTX);
+  const int k0 = (t / (nbx * nby)) * KZ, k1 = min(k0 + KZ, nz + 1);
+  if (i > nx || j > ny) return;
   const Idx I{nx, ny, nz};
   const size_t nu = (size_t)(nx + 1) * ny * nz, nv = (size_t)nx * (ny + 1) * nz;
   const double* src = accumulate ? v : w;
   // branch-free loads: in-range clamped cell indices, wall faces selected to 0
-  const int ic = min(i, nx - 1), jc = min(j, ny - 1), kc = min(k, nz - 1);
-  const double pc = phi[I.c(kc, jc, ic)];
-  if (j < ny && k < nz) {
-    const size_t q = I.u(k, j, i);
-    const bool in = (i > 0) & (i < nx);
-    const double pw = phi[I.c(k, j, max(i - 1, 0))], pe = phi[I.c(k, j, ic)], s = src[q];
-    const double val = s - (pe - pw) * g.x.rdd[i];
-    v[q] = in ? val : 0.0;
-  }
-  if (i < nx && k < nz) {
-    const size_t q = nu + I.v(k, j, i);
-    const bool in = (j > 0) & (j < ny);
-    const double ps = phi[I.c(k, max(j - 1, 0), i)], pn = phi[I.c(k, jc, i)], s = src[q];
-    const double val = s - (pn - ps) * g.y.rdd[j];
-    v[q] = in ? val : 0.0;
-  }
-  if (i < nx && j < ny) {
-    const size_t q = nu + nv + I.w(k, j, i);
-    const bool in = (k > 0) & (k < nz);
-    const double pb = phi[I.c(max(k - 1, 0), j, i)], s = src[q];
-    const double val = s - (pc - pb) * g.z.rdd[k];
-    v[q] = in ? val : 0.0;
-    if (p && k < nz) {
-      const size_t c = I.c(k, j, i);
-      p[c] = accumulate ? p[c] + pc : pc;
+  const int ic = min(i, nx - 1), jc = min(j, ny - 1);
+  const double rddx = g.x.rdd[i], rddy = g.y.rdd[j];
+  double pb = phi[I.c(max(k0 - 1, 0), jc, ic)];  // phi below the first plane
+  for (int k = k0; k < k1; ++k) {
+    const int kc = min(k, nz - 1);
+    const double pc = phi[I.c(kc, jc, ic)];
+    if (j < ny && k < nz) {
+      const size_t q = I.u(k, j, i);
+      const bool in = (i > 0) & (i < nx);
+      const double pw = phi[I.c(k, j, max(i - 1, 0))], s = src[q];
+      const double val = s - (pc - pw) * rddx;
+      v[q] = in ? val : 0.0;
     }
+    if (i < nx && k < nz) {
+      const size_t q = nu + I.v(k, j, i);
+      const bool in = (j > 0) & (j < ny);
+      const double ps = phi[I.c(k, max(j - 1, 0), i)], s = src[q];
+      const double val = s - (pc - ps) * rddy;
+      v[q] = in ? val : 0.0;
+    }
+    if (i < nx && j < ny) {
+      const size_t q = nu + nv + I.w(k, j, i);
+      const bool in = (k > 0) & (k < nz);
+      const double s = src[q];
+      const double val = s - (pc - pb) * g.z.rdd[k];
+      v[q] = in ? val : 0.0;
+      if (p && k < nz) {
+        const size_t c = I.c(k, j, i);
+        p[c] = accumulate ? p[c] + pc : pc;
+      }
+    }
+    pb = pc;
   }
 }
 
@@ -393,19 +414,20 @@ hipError_t launch_divergence(const GridDev& g, const double* v, double* r, doubl
   const int nx = g.x.n, ny = g.y.n, nz = g.z.n;
   const VelLayout L = vel_layout(nx, ny, nz);
   Vel V{v, v + L.ov(), v + L.ow(), Idx{nx, ny, nz}};
-  const size_t ncell = (size_t)nx * ny * nz;
-  const unsigned nb = blocks_for(ncell, kReduceBlock);
+  const int nbx = (int)blocks_for(nx, kDivTX), nby = (int)blocks_for(ny, kDivTY);
+  const unsigned nb = (unsigned)(nbx * nby * (int)blocks_for(nz, kDivKZ));
   if (nparts) *nparts = (int)nb;
-  hipLaunchKernelGGL(k_divergence, dim3(nb), dim3(kReduceBlock), 0, st, g, V, r, partials);
+  hipLaunchKernelGGL(k_divergence<kDivKZ>, dim3(nb), dim3(kDivTX * kDivTY), 0, st, g, V, r, partials, nbx, nby);
   return hipGetLastError();
 }
 
 hipError_t launch_correct(const GridDev& g, const double* w, const double* phi, double* v, double* p,
                           bool accumulate, hipStream_t st) {
   const int nx = g.x.n, ny = g.y.n, nz = g.z.n;
-  dim3 block(64, 4, 1);
-  dim3 grid(blocks_for(nx + 1, 64), blocks_for(ny + 1, 4), nz + 1);
-  hipLaunchKernelGGL(k_correct, grid, block, 0, st, g, w, phi, v, p, accumulate ? 1 : 0);
+  const int nbx = (int)blocks_for(nx + 1, kCorTX), nby = (int)blocks_for(ny + 1, kCorTY);
+  const unsigned nb = (unsigned)(nbx * nby * (int)blocks_for(nz + 1, kCorKZ));
+  hipLaunchKernelGGL(k_correct<kCorKZ>, dim3(nb), dim3(kCorTX * kCorTY), 0, st, g, w, phi, v, p, accumulate ? 1 : 0, nbx,
+                     nby);
   return hipGetLastError();
 }
 

@@ -109,8 +109,9 @@ int upload_grid(lc_ctx* c) {
   for (int a = 0; a < 3; ++a) {
     const size_t nn = (size_t)n[a] * n[a];
     const size_t half = 3 * nn;
+    const size_t he = (n[a] + 1) / 2, packs = 4 * (size_t)mf_steps((int)he) * ((he + 15) / 16) * 64;
     mbytes += 2 * n[a] * sizeof(double) + 4 * nn * sizeof(double) + 4 * nn * sizeof(float) +
-              half * (sizeof(double) + sizeof(float));
+              (half + packs) * (sizeof(double) + sizeof(float));
   }
   if (!c->modes_mem) HIPCHK(c, hipMalloc(&c->modes_mem, mbytes));
   std::vector<char> mhost(mbytes);
@@ -164,6 +165,7 @@ int upload_grid(lc_ctx* c) {
                 !neumann_half_modes(m, AH.d.data(), AH.dd.data(), true, lam_o, Sh_o)))
       return fail(c, LC_EINVAL, "tridiagonal eigen-solver did not converge on axis %d (half problems)", a);
     M.sym = sym;
+    M.mf = false;
     M.he = he;
     M.ho = ho;
     if (sym) {
@@ -205,6 +207,24 @@ int upload_grid(lc_ctx* c) {
       put_d(lam_s, &M.lam_s);
       for (int q = 0; q < 8; ++q) put_d(h[q], &M.h64[q]);
       for (int q = 0; q < 8; ++q) put_f(h[q], &M.h32[q]);
+      // fragment packs for the matrix-core transforms: P[(kq * RT + t) * 64 + l] =
+      // Mat[o = 16 t + l % 16][k = 4 kq + l / 16], zero outside the matrix
+      M.mf = he <= kMfMaxHalf;
+      if (M.mf) {
+        const int RT = (he + 15) / 16, KQ = mf_steps(he);
+        const int rows[4] = {he, ho, he, he}, cols[4] = {he, ho, he, ho};
+        for (int q = 0; q < 4; ++q) {
+          std::vector<double> P((size_t)KQ * RT * 64, 0.0);
+          for (int kq = 0; kq < KQ; ++kq)
+            for (int t = 0; t < RT; ++t)
+              for (int l = 0; l < 64; ++l) {
+                const int o = 16 * t + l % 16, k = 4 * kq + l / 16;
+                if (o < rows[q] && k < cols[q]) P[((size_t)kq * RT + t) * 64 + l] = h[q][(size_t)o * cols[q] + k];
+              }
+          put_d(P, &M.p64[q]);
+          put_f(P, &M.p32[q]);
+        }
+      }
     }
   }
   HIPCHK(c, hipMemcpyAsync(c->modes_mem, mhost.data(), mbytes, hipMemcpyHostToDevice, c->stream));
@@ -234,6 +254,12 @@ int tp_solve(lc_ctx* c, const T* r, T* phi, T* t1, T* t2) {
     else
       return (const T*)M.h32[which];
   };
+  auto packs = [](const AxisModes& M, int which) -> const T* {
+    if constexpr (sizeof(T) == sizeof(double))
+      return (const T*)M.p64[which];
+    else
+      return (const T*)M.p32[which];
+  };
   auto lams = [](const AxisModes& M) { return M.sym ? M.lam_s : M.lam; };
   const AxisModes &X = c->modes[0], &Y = c->modes[1], &Z = c->modes[2];
   hipStream_t s = c->stream;
@@ -242,32 +268,47 @@ int tp_solve(lc_ctx* c, const T* r, T* phi, T* t1, T* t2) {
   // forward: x (contiguous lines), y (columns (k, i), rows nx apart), z (rows nx*ny apart),
   // the division by lam_x + lam_y + lam_z fused into the z transform; a mirror-symmetric
   // axis uses the folded half-size transforms (modes parity-sorted)
-  if (X.sym)
+  // (mirror-symmetric axes with he <= kMfMaxHalf run on the matrix cores)
+  if (X.mf)
+    KLAUNCH(c, LC_K_TP_X, launch_mff_right<T>(nx, n_yz, r, packs(X, 0), packs(X, 1), t1, s));
+  else if (X.sym)
     KLAUNCH(c, LC_K_TP_X, launch_tpf_right<T>(nx, n_yz, r, half(X, 4), half(X, 5), t1, s));
   else
     KLAUNCH(c, LC_K_TP_X, launch_tp_right<T>(n_yz, nx, nx, r, pick(X, 2), t1, s));
-  if (Y.sym)
+  if (Y.mf)
+    KLAUNCH(c, LC_K_TP_Y, launch_mff_left<T>(ny, n_xz, packs(Y, 0), packs(Y, 1), t1, t2, nx, pl, nx, s));
+  else if (Y.sym)
     KLAUNCH(c, LC_K_TP_Y, launch_tpf_left<T>(ny, n_xz, half(Y, 0), half(Y, 1), t1, t2, nx, pl, nx, nul, nul, nul, 1, 0, 0,
                                              0, s));
   else
     KLAUNCH(c, LC_K_TP_Y, launch_tp_left<T>(ny, n_xz, ny, pick(Y, 0), t1, t2, nx, pl, nx, nul, nul, nul, 1, 0, 0, 0, s));
-  if (Z.sym)
+  if (Z.mf)  // (the eigenvalue division then happens in the backward z transform)
+    KLAUNCH(c, LC_K_TP_Z, launch_mff_left<T>(nz, (int)pl, packs(Z, 0), packs(Z, 1), t2, t1, (int)pl, 0, pl, s));
+  else if (Z.sym)
     KLAUNCH(c, LC_K_TP_Z, launch_tpf_left<T>(nz, (int)pl, half(Z, 0), half(Z, 1), t2, t1, (int)pl, 0, pl, lams(Z),
                                              lams(Y), lams(X), nx, c->zero_mode[2], c->zero_mode[1], c->zero_mode[0], s));
   else
     KLAUNCH(c, LC_K_TP_Z, launch_tp_left<T>(nz, (int)pl, nz, pick(Z, 0), t2, t1, (int)pl, 0, pl, lams(Z), lams(Y),
                                             lams(X), nx, c->zero_mode[2], c->zero_mode[1], c->zero_mode[0], s));
   // backward: z, y, x
-  if (Z.sym)
+  if (Z.mf)
+    KLAUNCH(c, LC_K_TP_Z, launch_mfu_left<T>(nz, (int)pl, packs(Z, 2), packs(Z, 3), t1, t2, (int)pl, 0, pl, lams(Z),
+                                             lams(Y), lams(X), nx, c->zero_mode[2], c->zero_mode[1], c->zero_mode[0], s));
+  else if (Z.sym)
     KLAUNCH(c, LC_K_TP_Z, launch_tpu_left<T>(nz, (int)pl, half(Z, 2), half(Z, 3), t1, t2, (int)pl, 0, pl, s));
   else
     KLAUNCH(c, LC_K_TP_Z, launch_tp_left<T>(nz, (int)pl, nz, pick(Z, 1), t1, t2, (int)pl, 0, pl, nul, nul, nul, 1, 0, 0,
                                             0, s));
-  if (Y.sym)
+  if (Y.mf)
+    KLAUNCH(c, LC_K_TP_Y, launch_mfu_left<T>(ny, n_xz, packs(Y, 2), packs(Y, 3), t2, t1, nx, pl, nx, nul, nul, nul, 1, 0,
+                                             0, 0, s));
+  else if (Y.sym)
     KLAUNCH(c, LC_K_TP_Y, launch_tpu_left<T>(ny, n_xz, half(Y, 2), half(Y, 3), t2, t1, nx, pl, nx, s));
   else
     KLAUNCH(c, LC_K_TP_Y, launch_tp_left<T>(ny, n_xz, ny, pick(Y, 1), t2, t1, nx, pl, nx, nul, nul, nul, 1, 0, 0, 0, s));
-  if (X.sym)
+  if (X.mf)
+    KLAUNCH(c, LC_K_TP_X, launch_mfu_right<T>(nx, n_yz, t1, packs(X, 2), packs(X, 3), phi, s));
+  else if (X.sym)
     KLAUNCH(c, LC_K_TP_X, launch_tpu_right<T>(nx, n_yz, t1, half(X, 6), half(X, 7), phi, s));
   else
     KLAUNCH(c, LC_K_TP_X, launch_tp_right<T>(n_yz, nx, nx, t1, pick(X, 3), phi, s));

@@ -46,6 +46,10 @@ struct AxisModes {
   // [4] FTe (he x he), [5] FTo (ho x ho), [6] SeT (he x he), [7] SoT (ho x he)
   double* h64[8] = {};
   float* h32[8] = {};
+  // matrix-core fragment packs of Ae, Ao, Se, So (he <= kMfMaxHalf)
+  bool mf = false;
+  double* p64[4] = {};
+  float* p32[4] = {};
 };
 
 }  // namespace lk

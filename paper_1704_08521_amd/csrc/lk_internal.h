@@ -118,6 +118,29 @@ hipError_t launch_tpf_right(int n, int Mlines, const T* A, const T* Be, const T*
 template <typename T>
 hipError_t launch_tpu_right(int n, int Mlines, const T* A, const T* SeT, const T* SoT, T* C, hipStream_t st);
 
+// The same four transforms on the matrix cores, for he = ceil(n/2) <= 128 (kMfMaxHalf).
+// The half matrices are passed as fragment packs: Pe, Po packs of Ae, Ao (forward), Pse,
+// Pso packs of Se, So (backward), for the left and the right kernels alike
+// (P[(kq * RT + t) * 64 + l] = Mat[16 t + l % 16][4 kq + l / 16], RT = ceil(he / 16),
+// kq < mf_steps(he), zero outside the matrix: the contraction steps of 4 are padded to a
+// multiple of the kernels' prefetch depth kMfPD).  Here the eigenvalue scaling (lm, ly,
+// lx, zero mode) belongs to the backward left transform: its input modes are scaled on
+// load.
+constexpr int kMfMaxHalf = 128;
+constexpr int kMfPD = 2;
+__host__ __device__ constexpr int mf_steps(int he, int pd = kMfPD) { return ((he + 3) / 4 + pd - 1) / pd * pd; }
+template <typename T>
+hipError_t launch_mff_left(int n, int N, const T* Pe, const T* Po, const T* B, T* C, int nseg, long seg_stride,
+                           long kstride, hipStream_t st);
+template <typename T>
+hipError_t launch_mfu_left(int n, int N, const T* Pse, const T* Pso, const T* B, T* C, int nseg, long seg_stride,
+                           long kstride, const double* lm, const double* ly, const double* lx, int nxs, int zm, int zj,
+                           int zi, hipStream_t st);
+template <typename T>
+hipError_t launch_mff_right(int n, int Mlines, const T* A, const T* Pe, const T* Po, T* C, hipStream_t st);
+template <typename T>
+hipError_t launch_mfu_right(int n, int Mlines, const T* A, const T* Pse, const T* Pso, T* C, hipStream_t st);
+
 // Precision casts.
 hipError_t launch_d2f(size_t n, const double* in, float* out, hipStream_t st);
 // out = in (float -> double), or out += in when accumulate

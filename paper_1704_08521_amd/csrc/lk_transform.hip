@@ -616,6 +616,317 @@ hipError_t right_launch(int M, int N, int K, const T* A, const T* B, T* C, hipSt
   return hipGetLastError();
 }
 
+
+// ------------------------------------------------ matrix-core (MFMA) transforms
+// The folded transforms of a mirror-symmetric axis as 16x16x4 MFMA contractions
+// (FP64 or FP32 matrix cores).  One wave owns W tiles of 16 columns (left) or 16
+// lines (right) and every output mode of both parities, so each input value is read
+// from HBM once and folded in registers; no LDS.  The half matrices come packed in
+// fragment order: P[(kq * RT + t) * 64 + l] = Mat(o = 16 t + l % 16, k = 4 kq + l / 16),
+// zero outside the matrix, where o is the output index (mode forward, point backward)
+// and k the contracted one.  One 64-value load per fragment, and the same pack serves
+// as the A operand (left: Mat x data) and as the B operand (right: data x Mat^T).
+// Lane l of a 16x16x4 step holds A[l % 16][l / 16] and B[l / 16][l % 16]; it receives
+// D[row(l / 16, r)][l % 16], r = 0..3, with row = 4 g + r (FP32) or g + 4 r (FP64), as
+// measured on gfx950.
+template <typename T>
+struct Mf;
+template <>
+struct Mf<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 mma(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int g, int r) { return g + 4 * r; }
+};
+template <>
+struct Mf<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 mma(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int g, int r) { return 4 * g + r; }
+};
+
+// v / a for the eigenvalue scaling, a > 0: hardware reciprocal refined by two Newton
+// steps and one residual correction of the quotient (within an ulp of v / a, a third of
+// the instructions of the IEEE division sequence).
+__device__ __forceinline__ double mf_div(double v, double a) {
+  double y = __builtin_amdgcn_rcp(a);
+  double e = fma(-a, y, 1.0);
+  y = fma(e, y, y);
+  e = fma(-a, y, 1.0);
+  y = fma(e, y, y);
+  const double q = v * y;
+  return fma(fma(-a, q, v), y, q);
+}
+
+// Data fragments of contraction index k (= 4 kq + l / 16) for the W tiles: element
+// (tile c, k) lives at src[base[c] + k * kstr].  mf_load issues the two raw loads (k and
+// its mirror n-1-k forward, the even mode k and the odd mode he+k backward) from
+// in-range addresses; mf_fold combines them only when the step is computed, so the loads
+// stay in flight meanwhile.  Forward: s = f_k + f_{n-1-k} (f_k alone on the middle row),
+// d = f_k - f_{n-1-k}.  Backward: s = c_k, d = c_{he+k}.
+template <typename T, int W, bool FOLD>
+__device__ __forceinline__ void mf_load(const T* __restrict__ src, const long (&base)[W], const bool (&ok)[W],
+                                        long kstr, int n, int he, int ho, int k, T (&x1)[W], T (&x2)[W]) {
+  const bool ke = k < he, ko = k < ho;
+  const long k1 = k, k2 = FOLD ? (long)(n - 1 - k) : (long)(he + k);
+#pragma unroll
+  for (int c = 0; c < W; ++c) {
+    const bool oe = ok[c] & ke, oo = ok[c] & (FOLD ? ke : ko);
+    x1[c] = src[oe ? base[c] + k1 * kstr : 0];
+    x2[c] = src[oo ? base[c] + k2 * kstr : 0];
+  }
+}
+// Optional scaling of the backward operands (SCALE: the pressure solve's division by the
+// sum of the axis eigenvalues, done where the z backward transform loads its modes):
+// column c's mode k is divided by lm[k] + sxy[c], and the constant mode (zm in a
+// zero-mode column, zc[c]) is set to zero.
+template <typename T, int W, bool FOLD, bool SCALE>
+__device__ __forceinline__ void mf_fold(const bool (&ok)[W], int n, int he, int ho, int k, const T (&x1)[W],
+                                        const T (&x2)[W], int zm, double le, double lo, const double (&sxy)[W],
+                                        const bool (&zc)[W], T (&s)[W], T (&d)[W]) {
+  const bool ke = k < he, ko = k < ho;
+#pragma unroll
+  for (int c = 0; c < W; ++c) {
+    const bool oe = ok[c] & ke;
+    if (FOLD) {
+      s[c] = oe ? (n - 1 - k == k ? x1[c] : x1[c] + x2[c]) : T(0);
+      d[c] = (oe & ko) ? x1[c] - x2[c] : T(0);
+    } else if (SCALE) {  // padding and the constant mode stay exactly zero (no 0/0)
+      s[c] = (!oe || (zc[c] && k == zm)) ? T(0) : (T)mf_div((double)x1[c], le + sxy[c]);
+      d[c] = (!(ok[c] & ko) || (zc[c] && he + k == zm)) ? T(0) : (T)mf_div((double)x2[c], lo + sxy[c]);
+    } else {
+      s[c] = oe ? x1[c] : T(0);
+      d[c] = (ok[c] & ko) ? x2[c] : T(0);
+    }
+  }
+}
+
+// Accumulates the even and odd contractions of one wave: acc_e += Pe x s, acc_o += Po x d
+// over the KQP steps of the (padded) packs.  Vector-memory loads complete in issue order,
+// so every load of a step - raw data (HBM), pack fragments (L1/L2) and eigenvalues alike -
+// is issued PD steps ahead into a register ring; the step loop has no conditional exits
+// (KQP is a multiple of PD, the padding steps hold zero fragments and masked data), which
+// lets the compiler wait for exactly the oldest step's loads instead of draining all of
+// them at the loop head.  LEFT: the pack is the A operand; otherwise the data is.
+template <typename T, int RT, int W, bool FOLD, bool LEFT, bool SCALE, int PD>
+__device__ __forceinline__ void mf_contract(const T* __restrict__ Pe, const T* __restrict__ Po,
+                                            const T* __restrict__ src, const long (&base)[W], const bool (&ok)[W],
+                                            long kstr, int n, int he, int ho, const double* __restrict__ lm, int zm,
+                                            const double (&sxy)[W], const bool (&zc)[W],
+                                            typename Mf<T>::v4 (&ae)[RT][W], typename Mf<T>::v4 (&ao)[RT][W]) {
+  const int lane = threadIdx.x & 63, g = lane >> 4;
+  const int KQP = mf_steps(he, PD);
+#pragma unroll
+  for (int t = 0; t < RT; ++t)
+#pragma unroll
+    for (int c = 0; c < W; ++c) {
+      ae[t][c] = typename Mf<T>::v4{0, 0, 0, 0};
+      ao[t][c] = typename Mf<T>::v4{0, 0, 0, 0};
+    }
+  T pe[PD][RT], po[PD][RT], r1[PD][W], r2[PD][W];
+  double le[PD], lo[PD];
+#define LK_MF_ISSUE(u, kq)                                                              \
+  {                                                                                     \
+    const int kc = min(kq, KQP - 1); /* the last steps re-read in-range fragments */    \
+    _Pragma("unroll") for (int t = 0; t < RT; ++t) {                                    \
+      pe[u][t] = Pe[(kc * RT + t) * 64 + lane];                                         \
+      po[u][t] = Po[(kc * RT + t) * 64 + lane];                                         \
+    }                                                                                   \
+    mf_load<T, W, FOLD>(src, base, ok, kstr, n, he, ho, 4 * kc + g, r1[u], r2[u]);      \
+    if (SCALE) {                                                                        \
+      le[u] = lm[min(4 * kc + g, he - 1)];                                              \
+      lo[u] = lm[he + min(4 * kc + g, max(ho - 1, 0))];                                 \
+    } else {                                                                            \
+      le[u] = lo[u] = 1.0;                                                              \
+    }                                                                                   \
+  }
+#pragma unroll
+  for (int u = 0; u < PD; ++u) LK_MF_ISSUE(u, u)
+  for (int kq0 = 0; kq0 < KQP; kq0 += PD) {
+#pragma unroll
+    for (int u = 0; u < PD; ++u) {
+      const int kq = kq0 + u;
+      T s[W], d[W];
+      mf_fold<T, W, FOLD, SCALE>(ok, n, he, ho, 4 * kq + g, r1[u], r2[u], zm, le[u], lo[u], sxy, zc, s, d);
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int c = 0; c < W; ++c) {
+          if (LEFT) {
+            ae[t][c] = Mf<T>::mma(pe[u][t], s[c], ae[t][c]);
+            ao[t][c] = Mf<T>::mma(po[u][t], d[c], ao[t][c]);
+          } else {
+            ae[t][c] = Mf<T>::mma(s[c], pe[u][t], ae[t][c]);
+            ao[t][c] = Mf<T>::mma(d[c], po[u][t], ao[t][c]);
+          }
+        }
+      LK_MF_ISSUE(u, kq + PD)
+    }
+  }
+#undef LK_MF_ISSUE
+}
+
+// Left, forward (folded); layout as k_tpf_left (the eigenvalue scaling is left to the
+// backward transform).
+template <typename T, int RT, int W, int PD, int LB>
+__global__ void __launch_bounds__(256, LB) k_mff_left(int n, int he, int ho, int N, const T* __restrict__ Pe,
+                                                  const T* __restrict__ Po, const T* __restrict__ B, T* __restrict__ C,
+                                                  int nseg, long seg_stride, long kstride) {
+  const int lane = threadIdx.x & 63, g = lane >> 4, cl = lane & 15;
+  const int col0 = (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 16 * W;
+  if (col0 >= N) return;
+  long base[W];
+  bool ok[W], zc[W];
+  double sxy[W];
+#pragma unroll
+  for (int c = 0; c < W; ++c) {
+    const int col = col0 + 16 * c + cl;
+    ok[c] = col < N;
+    base[c] = ok[c] ? (long)(col / nseg) * seg_stride + col % nseg : 0;
+    zc[c] = false;
+    sxy[c] = 0.0;
+  }
+  typename Mf<T>::v4 ae[RT][W], ao[RT][W];
+  mf_contract<T, RT, W, true, true, false, PD>(Pe, Po, B, base, ok, kstride, n, he, ho, nullptr, -1, sxy, zc, ae, ao);
+#pragma unroll
+  for (int c = 0; c < W; ++c) {
+    if (!ok[c]) continue;
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int o = 16 * t + Mf<T>::row(g, r);
+        if (o < he) C[base[c] + (long)o * kstride] = ae[t][c][r];
+        if (o < ho) C[base[c] + (long)(he + o) * kstride] = ao[t][c][r];
+      }
+  }
+}
+
+// Left, backward (unfolded); layout as k_tpu_left.
+// With lm set, the input modes are first divided by lm[mode] + ly[j] + lx[i] (column
+// (j, i) = (col / nxs, col % nxs)) and the constant mode (zm, zj, zi) is zeroed.
+template <typename T, int RT, int W, bool SCALE, int PD, int LB>
+__global__ void __launch_bounds__(256, LB) k_mfu_left(int n, int he, int ho, int N, const T* __restrict__ Pse,
+                                                  const T* __restrict__ Pso, const T* __restrict__ B, T* __restrict__ C,
+                                                  int nseg, long seg_stride, long kstride, const double* __restrict__ lm,
+                                                  const double* __restrict__ ly, const double* __restrict__ lx, int nxs,
+                                                  int zm, int zj, int zi) {
+  const int lane = threadIdx.x & 63, g = lane >> 4, cl = lane & 15;
+  const int col0 = (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 16 * W;
+  if (col0 >= N) return;
+  long base[W];
+  bool ok[W], zc[W];
+  double sxy[W];
+#pragma unroll
+  for (int c = 0; c < W; ++c) {
+    const int col = col0 + 16 * c + cl;
+    ok[c] = col < N;
+    base[c] = ok[c] ? (long)(col / nseg) * seg_stride + col % nseg : 0;
+    const int jj = ok[c] && SCALE ? col / nxs : 0, ii = ok[c] && SCALE ? col % nxs : 0;
+    zc[c] = SCALE && jj == zj && ii == zi;
+    sxy[c] = SCALE ? ly[jj] + lx[ii] : 0.0;
+  }
+  typename Mf<T>::v4 aa[RT][W], ab[RT][W];
+  mf_contract<T, RT, W, false, true, SCALE, PD>(Pse, Pso, B, base, ok, kstride, n, he, ho, lm, zm, sxy, zc, aa, ab);
+#pragma unroll
+  for (int c = 0; c < W; ++c) {
+    if (!ok[c]) continue;
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 16 * t + Mf<T>::row(g, r);
+        const T va = aa[t][c][r], vb = ab[t][c][r];
+        if (i < he) C[base[c] + (long)i * kstride] = va + vb;
+        if (i < ho) C[base[c] + (long)(n - 1 - i) * kstride] = va - vb;
+      }
+  }
+}
+
+// Right, forward (folded): lines of n contiguous values in A, C.
+template <typename T, int RT, int W, int PD, int LB>
+__global__ void __launch_bounds__(256, LB) k_mff_right(int n, int he, int ho, int Mlines, const T* __restrict__ A,
+                                                   const T* __restrict__ Pe, const T* __restrict__ Po,
+                                                   T* __restrict__ C) {
+  const int lane = threadIdx.x & 63, g = lane >> 4, cl = lane & 15;
+  const int line0 = (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 16 * W;
+  if (line0 >= Mlines) return;
+  long base[W];
+  bool ok[W];
+#pragma unroll
+  for (int c = 0; c < W; ++c) {
+    const int line = line0 + 16 * c + cl;
+    ok[c] = line < Mlines;
+    base[c] = ok[c] ? (long)line * n : 0;
+  }
+  typename Mf<T>::v4 ae[RT][W], ao[RT][W];
+  bool zc[W];
+  double sxy[W];
+#pragma unroll
+  for (int c = 0; c < W; ++c) {
+    zc[c] = false;
+    sxy[c] = 0.0;
+  }
+  mf_contract<T, RT, W, true, false, false, PD>(Pe, Po, A, base, ok, 1, n, he, ho, nullptr, -1, sxy, zc, ae, ao);
+#pragma unroll
+  for (int c = 0; c < W; ++c)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int line = line0 + 16 * c + Mf<T>::row(g, r);
+      if (line >= Mlines) continue;
+#pragma unroll
+      for (int t = 0; t < RT; ++t) {
+        const int o = 16 * t + cl;
+        if (o < he) C[(long)line * n + o] = ae[t][c][r];
+        if (o < ho) C[(long)line * n + he + o] = ao[t][c][r];
+      }
+    }
+}
+
+// Right, backward (unfolded): lines of parity-sorted modes in A, of points in C.
+template <typename T, int RT, int W, int PD, int LB>
+__global__ void __launch_bounds__(256, LB) k_mfu_right(int n, int he, int ho, int Mlines, const T* __restrict__ A,
+                                                   const T* __restrict__ Pse, const T* __restrict__ Pso,
+                                                   T* __restrict__ C) {
+  const int lane = threadIdx.x & 63, g = lane >> 4, cl = lane & 15;
+  const int line0 = (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 16 * W;
+  if (line0 >= Mlines) return;
+  long base[W];
+  bool ok[W];
+#pragma unroll
+  for (int c = 0; c < W; ++c) {
+    const int line = line0 + 16 * c + cl;
+    ok[c] = line < Mlines;
+    base[c] = ok[c] ? (long)line * n : 0;
+  }
+  typename Mf<T>::v4 aa[RT][W], ab[RT][W];
+  bool zc[W];
+  double sxy[W];
+#pragma unroll
+  for (int c = 0; c < W; ++c) {
+    zc[c] = false;
+    sxy[c] = 0.0;
+  }
+  mf_contract<T, RT, W, false, false, false, PD>(Pse, Pso, A, base, ok, 1, n, he, ho, nullptr, -1, sxy, zc, aa, ab);
+#pragma unroll
+  for (int c = 0; c < W; ++c)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int line = line0 + 16 * c + Mf<T>::row(g, r);
+      if (line >= Mlines) continue;
+#pragma unroll
+      for (int t = 0; t < RT; ++t) {
+        const int i = 16 * t + cl;
+        const T va = aa[t][c][r], vb = ab[t][c][r];
+        if (i < he) C[(long)line * n + i] = va + vb;
+        if (i < ho) C[(long)line * n + (n - 1 - i)] = va - vb;
+      }
+    }
+}
+
 }  // namespace
 
 template <typename T>
@@ -784,5 +1095,85 @@ template hipError_t launch_tp_right<float>(int, int, int, const float*, const fl
 LK_TPF_INST(double)
 LK_TPF_INST(float)
 #undef LK_TPF_INST
+
+
+// ------------------------------------------------ matrix-core launchers
+// RT = ceil(he / 16) row tiles per wave (he <= 128); 4 waves per block.
+#define LK_MF_SWITCH(RT_, BODY) \
+  switch (RT_) {                \
+    case 1: BODY(1) break;      \
+    case 2: BODY(2) break;      \
+    case 3: BODY(3) break;      \
+    case 4: BODY(4) break;      \
+    case 5: BODY(5) break;      \
+    case 6: BODY(6) break;      \
+    case 7: BODY(7) break;      \
+    case 8: BODY(8) break;      \
+    default: return hipErrorInvalidValue; \
+  }
+// forward kernels keep their accumulators in AGPRs at 2 waves per SIMD by themselves;
+// the backward ones (a + b, a - b epilogue) need the 2-wave bound to get there
+constexpr int kMfW = 1, kMfLBf = 1, kMfLBu = 2;
+
+template <typename T>
+hipError_t launch_mff_left(int n, int N, const T* Pe, const T* Po, const T* B, T* C, int nseg, long seg_stride,
+                           long kstride, hipStream_t st) {
+  const int he = (n + 1) / 2, ho = n / 2;
+  const dim3 grid(blocks_for(blocks_for(N, 16 * kMfW), 4));
+#define BODY(RT) hipLaunchKernelGGL((k_mff_left<T, RT, kMfW, kMfPD, kMfLBf>), grid, dim3(256), 0, st, n, he, ho, N, Pe, Po, B, C, nseg, \
+                                    seg_stride, kstride);
+  LK_MF_SWITCH((he + 15) / 16, BODY)
+#undef BODY
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_mfu_left(int n, int N, const T* Pse, const T* Pso, const T* B, T* C, int nseg, long seg_stride,
+                           long kstride, const double* lm, const double* ly, const double* lx, int nxs, int zm, int zj,
+                           int zi, hipStream_t st) {
+  const int he = (n + 1) / 2, ho = n / 2;
+  const dim3 grid(blocks_for(blocks_for(N, 16 * kMfW), 4));
+#define BODY(RT)                                                                                                   \
+  if (lm)                                                                                                          \
+    hipLaunchKernelGGL((k_mfu_left<T, RT, kMfW, true, kMfPD, kMfLBu>), grid, dim3(256), 0, st, n, he, ho, N, Pse, Pso, B, C, nseg,  \
+                       seg_stride, kstride, lm, ly, lx, nxs, zm, zj, zi);                                          \
+  else                                                                                                             \
+    hipLaunchKernelGGL((k_mfu_left<T, RT, kMfW, false, kMfPD, kMfLBu>), grid, dim3(256), 0, st, n, he, ho, N, Pse, Pso, B, C, nseg, \
+                       seg_stride, kstride, lm, ly, lx, nxs, zm, zj, zi);
+  LK_MF_SWITCH((he + 15) / 16, BODY)
+#undef BODY
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_mff_right(int n, int Mlines, const T* A, const T* Pe, const T* Po, T* C, hipStream_t st) {
+  const int he = (n + 1) / 2, ho = n / 2;
+  const dim3 grid(blocks_for(blocks_for(Mlines, 16 * kMfW), 4));
+#define BODY(RT) hipLaunchKernelGGL((k_mff_right<T, RT, kMfW, kMfPD, kMfLBf>), grid, dim3(256), 0, st, n, he, ho, Mlines, A, Pe, Po, C);
+  LK_MF_SWITCH((he + 15) / 16, BODY)
+#undef BODY
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_mfu_right(int n, int Mlines, const T* A, const T* Pse, const T* Pso, T* C, hipStream_t st) {
+  const int he = (n + 1) / 2, ho = n / 2;
+  const dim3 grid(blocks_for(blocks_for(Mlines, 16 * kMfW), 4));
+#define BODY(RT) hipLaunchKernelGGL((k_mfu_right<T, RT, kMfW, kMfPD, kMfLBu>), grid, dim3(256), 0, st, n, he, ho, Mlines, A, Pse, Pso, C);
+  LK_MF_SWITCH((he + 15) / 16, BODY)
+#undef BODY
+  return hipGetLastError();
+}
+#undef LK_MF_SWITCH
+
+#define LK_MF_INST(T)                                                                                            \
+  template hipError_t launch_mff_left<T>(int, int, const T*, const T*, const T*, T*, int, long, long, hipStream_t); \
+  template hipError_t launch_mfu_left<T>(int, int, const T*, const T*, const T*, T*, int, long, long, const double*, \
+                                         const double*, const double*, int, int, int, int, hipStream_t);          \
+  template hipError_t launch_mff_right<T>(int, int, const T*, const T*, const T*, T*, hipStream_t);                \
+  template hipError_t launch_mfu_right<T>(int, int, const T*, const T*, const T*, T*, hipStream_t);
+LK_MF_INST(double)
+LK_MF_INST(float)
+#undef LK_MF_INST
 
 }  // namespace lk

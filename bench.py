@@ -25,7 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-PEAK_FP64_VECTOR_TFLOPS = 78.6
+PEAK_FP64_TFLOPS = 78.6
 PEAK_BF16_TFLOPS = 2500.0
 # multiply-adds x 2 per voxel of the network's padded grid: 3x3x3 convs 4->16, 16->32 (1/8 of
 # the voxels), 32->64 (1/64), 96->32 (1/8), 48->16, and the 16->1 head
@@ -146,7 +146,7 @@ def kernel_table(prof, n, symmetric=True):
                 row["frac_hbm"] = row["GB/s"] / PEAK_HBM_GBS
             else:
                 row["TFLOP/s"] = amount / (avg * 1e-3) / 1e12
-                row["frac_fp64"] = row["TFLOP/s"] / PEAK_FP64_VECTOR_TFLOPS
+                row["frac_fp64"] = row["TFLOP/s"] / PEAK_FP64_TFLOPS
             row["algorithmic"] = amount
         table[name] = row
     return table
@@ -283,7 +283,8 @@ def main():
     dom = max((k for k in table if "algorithmic" in table[k]), key=lambda k: table[k]["total_ms"])
     d = table[dom]
     if "TFLOP/s" in d:
-        roof = {"bound": "alu", "achieved": d["TFLOP/s"], "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
+        # the symmetric-grid transforms run on the FP64 matrix cores (same 78.6 TFLOP/s peak)
+        roof = {"bound": "mfma", "achieved": d["TFLOP/s"], "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                 "frac": d["frac_fp64"], "traffic": profile_traffic(dom, n), "kernel": dom, "avg_ms": d["avg_ms"]}
     else:
         roof = {"bound": "hbm", "achieved": d["GB/s"], "peak": PEAK_HBM_GBS, "unit": "GB/s",

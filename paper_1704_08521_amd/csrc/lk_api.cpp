@@ -109,14 +109,17 @@ int upload_grid(lc_ctx* c) {
   for (int a = 0; a < 3; ++a) {
     const size_t nn = (size_t)n[a] * n[a];
     const size_t half = 3 * nn;
-    const size_t he = (n[a] + 1) / 2, packs = 4 * (size_t)mf_steps((int)he) * ((he + 15) / 16) * 64;
+    const int he = (n[a] + 1) / 2;
     mbytes += 2 * n[a] * sizeof(double) + 4 * nn * sizeof(double) + 4 * nn * sizeof(float) +
-              (half + packs) * (sizeof(double) + sizeof(float));
+              half * (sizeof(double) + sizeof(float)) + 4 * (mf_pack_size(he, 2) * sizeof(double) +
+                                                             mf_pack_size(he, 4) * sizeof(float)) +
+              64 * 16;  // alignment padding (at most 15 bytes for each of an axis' <= 34 arrays)
   }
   if (!c->modes_mem) HIPCHK(c, hipMalloc(&c->modes_mem, mbytes));
   std::vector<char> mhost(mbytes);
   char* hp = mhost.data();
   char* dp = (char*)c->modes_mem;
+  bool overflow = false;
   for (int a = 0; a < 3; ++a) {
     const int m = n[a];
     const size_t nn = (size_t)m * m;
@@ -131,13 +134,28 @@ int upload_grid(lc_ctx* c) {
         BkT[(size_t)j * m + i] = Bk[(size_t)i * m + j];
       }
     AxisModes& M = c->modes[a];
+    // every array starts 16-byte aligned (the matrix-core kernels read packs 16 bytes a lane)
+    auto align16 = [&]() {
+      const size_t pad = (16 - (size_t)(hp - mhost.data()) % 16) % 16;
+      hp += pad;
+      dp += pad;
+    };
+    auto fits = [&](size_t bytes) {  // never write past the host staging buffer
+      if ((size_t)(hp - mhost.data()) + bytes <= mbytes) return true;
+      overflow = true;
+      return false;
+    };
     auto put_d = [&](const std::vector<double>& v, double** dptr) {
+      align16();
+      if (!fits(v.size() * sizeof(double))) return;
       std::memcpy(hp, v.data(), v.size() * sizeof(double));
       *dptr = (double*)dp;
       hp += v.size() * sizeof(double);
       dp += v.size() * sizeof(double);
     };
     auto put_f = [&](const std::vector<double>& v, float** dptr) {
+      align16();
+      if (!fits(v.size() * sizeof(float))) return;
       for (size_t q = 0; q < v.size(); ++q) ((float*)hp)[q] = (float)v[q];
       *dptr = (float*)dp;
       hp += v.size() * sizeof(float);
@@ -207,26 +225,32 @@ int upload_grid(lc_ctx* c) {
       put_d(lam_s, &M.lam_s);
       for (int q = 0; q < 8; ++q) put_d(h[q], &M.h64[q]);
       for (int q = 0; q < 8; ++q) put_f(h[q], &M.h32[q]);
-      // fragment packs for the matrix-core transforms: P[(kq * RT + t) * 64 + l] =
-      // Mat[o = 16 t + l % 16][k = 4 kq + l / 16], zero outside the matrix
+      // fragment packs for the matrix-core transforms: fragment (kq, t, l) =
+      // Mat[o = 16 t + l % 16][k = 4 kq + l / 16], zero outside the matrix, laid out by
+      // mf_pack_index (two FP64 / four FP32 fragments per 16-byte lane load)
       M.mf = he <= kMfMaxHalf;
       if (M.mf) {
         const int RT = (he + 15) / 16, KQ = mf_steps(he);
         const int rows[4] = {he, ho, he, he}, cols[4] = {he, ho, he, ho};
         for (int q = 0; q < 4; ++q) {
-          std::vector<double> P((size_t)KQ * RT * 64, 0.0);
+          std::vector<double> P2(mf_pack_size(he, 2), 0.0), P4(mf_pack_size(he, 4), 0.0);
           for (int kq = 0; kq < KQ; ++kq)
             for (int t = 0; t < RT; ++t)
               for (int l = 0; l < 64; ++l) {
                 const int o = 16 * t + l % 16, k = 4 * kq + l / 16;
-                if (o < rows[q] && k < cols[q]) P[((size_t)kq * RT + t) * 64 + l] = h[q][(size_t)o * cols[q] + k];
+                if (o < rows[q] && k < cols[q]) {
+                  const double v = h[q][(size_t)o * cols[q] + k];
+                  P2[mf_pack_index(kq, t, l, RT, 2)] = v;
+                  P4[mf_pack_index(kq, t, l, RT, 4)] = v;
+                }
               }
-          put_d(P, &M.p64[q]);
-          put_f(P, &M.p32[q]);
+          put_d(P2, &M.p64[q]);
+          put_f(P4, &M.p32[q]);
         }
       }
     }
   }
+  if (overflow) return fail(c, LC_ENOMEM, "mode storage sized too small (internal)");
   HIPCHK(c, hipMemcpyAsync(c->modes_mem, mhost.data(), mbytes, hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->grid_ready = true;

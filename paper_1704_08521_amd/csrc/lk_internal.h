@@ -121,14 +121,23 @@ hipError_t launch_tpu_right(int n, int Mlines, const T* A, const T* SeT, const T
 // The same four transforms on the matrix cores, for he = ceil(n/2) <= 128 (kMfMaxHalf).
 // The half matrices are passed as fragment packs: Pe, Po packs of Ae, Ao (forward), Pse,
 // Pso packs of Se, So (backward), for the left and the right kernels alike
-// (P[(kq * RT + t) * 64 + l] = Mat[16 t + l % 16][4 kq + l / 16], RT = ceil(he / 16),
+// (fragment (kq, t, l) = Mat[16 t + l % 16][4 kq + l / 16], RT = ceil(he / 16),
 // kq < mf_steps(he), zero outside the matrix: the contraction steps of 4 are padded to a
-// multiple of the kernels' prefetch depth kMfPD).  Here the eigenvalue scaling (lm, ly,
+// multiple of the kernels' prefetch depth kMfPD; layout mf_pack_index).  Here the eigenvalue scaling (lm, ly,
 // lx, zero mode) belongs to the backward left transform: its input modes are scaled on
 // load.
 constexpr int kMfMaxHalf = 128;
 constexpr int kMfPD = 2;
 __host__ __device__ constexpr int mf_steps(int he, int pd = kMfPD) { return ((he + 3) / 4 + pd - 1) / pd * pd; }
+// Fragments are grouped fg = 16 / sizeof(element) per lane (one 16-byte load fetches fg
+// consecutive row tiles): fragment (kq, t, lane) sits at mf_pack_index(kq, t, lane, RT, fg).
+__host__ __device__ constexpr int mf_tile_groups(int RT, int fg) { return (RT + fg - 1) / fg; }
+__host__ __device__ constexpr long mf_pack_index(int kq, int t, int lane, int RT, int fg) {
+  return ((long)(kq * mf_tile_groups(RT, fg) + t / fg) * 64 + lane) * fg + t % fg;
+}
+__host__ __device__ constexpr long mf_pack_size(int he, int fg) {
+  return (long)mf_steps(he) * mf_tile_groups((he + 15) / 16, fg) * 64 * fg;
+}
 template <typename T>
 hipError_t launch_mff_left(int n, int N, const T* Pe, const T* Po, const T* B, T* C, int nseg, long seg_stride,
                            long kstride, hipStream_t st);

@@ -626,6 +626,7 @@ hipError_t right_launch(int M, int N, int K, const T* A, const T* B, T* C, hipSt
 // zero outside the matrix, where o is the output index (mode forward, point backward)
 // and k the contracted one.  One 64-value load per fragment, and the same pack serves
 // as the A operand (left: Mat x data) and as the B operand (right: data x Mat^T).
+// (Fragments are grouped 16 bytes per lane: see mf_pack_index.)
 // Lane l of a 16x16x4 step holds A[l % 16][l / 16] and B[l / 16][l % 16]; it receives
 // D[row(l / 16, r)][l % 16], r = 0..3, with row = 4 g + r (FP32) or g + 4 r (FP64), as
 // measured on gfx950.
@@ -650,7 +651,14 @@ struct Mf<float> {
 
 // v / a for the eigenvalue scaling, a > 0: hardware reciprocal refined by two Newton
 // steps and one residual correction of the quotient (within an ulp of v / a, a third of
-// the instructions of the IEEE division sequence).
+// the instructions of the IEEE division sequence).  The FP32 solve divides in FP32
+// (reciprocal and one Newton step).
+__device__ __forceinline__ float mf_div(float v, double a) {
+  const float af = (float)a;
+  float y = __builtin_amdgcn_rcpf(af);
+  y = fmaf(fmaf(-af, y, 1.0f), y, y);
+  return v * y;
+}
 __device__ __forceinline__ double mf_div(double v, double a) {
   double y = __builtin_amdgcn_rcp(a);
   double e = fma(-a, y, 1.0);
@@ -695,8 +703,8 @@ __device__ __forceinline__ void mf_fold(const bool (&ok)[W], int n, int he, int 
       s[c] = oe ? (n - 1 - k == k ? x1[c] : x1[c] + x2[c]) : T(0);
       d[c] = (oe & ko) ? x1[c] - x2[c] : T(0);
     } else if (SCALE) {  // padding and the constant mode stay exactly zero (no 0/0)
-      s[c] = (!oe || (zc[c] && k == zm)) ? T(0) : (T)mf_div((double)x1[c], le + sxy[c]);
-      d[c] = (!(ok[c] & ko) || (zc[c] && he + k == zm)) ? T(0) : (T)mf_div((double)x2[c], lo + sxy[c]);
+      s[c] = (!oe || (zc[c] && k == zm)) ? T(0) : mf_div(x1[c], le + sxy[c]);
+      d[c] = (!(ok[c] & ko) || (zc[c] && he + k == zm)) ? T(0) : mf_div(x2[c], lo + sxy[c]);
     } else {
       s[c] = oe ? x1[c] : T(0);
       d[c] = (ok[c] & ko) ? x2[c] : T(0);
@@ -726,14 +734,17 @@ __device__ __forceinline__ void mf_contract(const T* __restrict__ Pe, const T* _
       ae[t][c] = typename Mf<T>::v4{0, 0, 0, 0};
       ao[t][c] = typename Mf<T>::v4{0, 0, 0, 0};
     }
-  T pe[PD][RT], po[PD][RT], r1[PD][W], r2[PD][W];
+  constexpr int FG = 16 / sizeof(T), RTG = mf_tile_groups(RT, FG);
+  typedef T VG __attribute__((ext_vector_type(FG)));
+  VG pe[PD][RTG], po[PD][RTG];
+  T r1[PD][W], r2[PD][W];
   double le[PD], lo[PD];
 #define LK_MF_ISSUE(u, kq)                                                              \
   {                                                                                     \
     const int kc = min(kq, KQP - 1); /* the last steps re-read in-range fragments */    \
-    _Pragma("unroll") for (int t = 0; t < RT; ++t) {                                    \
-      pe[u][t] = Pe[(kc * RT + t) * 64 + lane];                                         \
-      po[u][t] = Po[(kc * RT + t) * 64 + lane];                                         \
+    _Pragma("unroll") for (int tg = 0; tg < RTG; ++tg) {                                \
+      pe[u][tg] = *(const VG*)(Pe + mf_pack_index(kc, tg * FG, lane, RT, FG));          \
+      po[u][tg] = *(const VG*)(Po + mf_pack_index(kc, tg * FG, lane, RT, FG));          \
     }                                                                                   \
     mf_load<T, W, FOLD>(src, base, ok, kstr, n, he, ho, 4 * kc + g, r1[u], r2[u]);      \
     if (SCALE) {                                                                        \
@@ -755,12 +766,13 @@ __device__ __forceinline__ void mf_contract(const T* __restrict__ Pe, const T* _
       for (int t = 0; t < RT; ++t)
 #pragma unroll
         for (int c = 0; c < W; ++c) {
+          const T fe = pe[u][t / FG][t % FG], fo = po[u][t / FG][t % FG];
           if (LEFT) {
-            ae[t][c] = Mf<T>::mma(pe[u][t], s[c], ae[t][c]);
-            ao[t][c] = Mf<T>::mma(po[u][t], d[c], ao[t][c]);
+            ae[t][c] = Mf<T>::mma(fe, s[c], ae[t][c]);
+            ao[t][c] = Mf<T>::mma(fo, d[c], ao[t][c]);
           } else {
-            ae[t][c] = Mf<T>::mma(s[c], pe[u][t], ae[t][c]);
-            ao[t][c] = Mf<T>::mma(d[c], po[u][t], ao[t][c]);
+            ae[t][c] = Mf<T>::mma(s[c], fe, ae[t][c]);
+            ao[t][c] = Mf<T>::mma(d[c], fo, ao[t][c]);
           }
         }
       LK_MF_ISSUE(u, kq + PD)
@@ -1112,8 +1124,11 @@ LK_TPF_INST(float)
     default: return hipErrorInvalidValue; \
   }
 // forward kernels keep their accumulators in AGPRs at 2 waves per SIMD by themselves;
-// the backward ones (a + b, a - b epilogue) need the 2-wave bound to get there
-constexpr int kMfW = 1, kMfLBf = 1, kMfLBu = 2;
+// the FP64 backward ones (a + b, a - b epilogue) need the 2-wave bound to get there (the
+// FP32 ones reach 5-6 waves unbounded and run slower bounded)
+constexpr int kMfW = 1, kMfLBf = 1;
+template <typename T>
+constexpr int mf_lbu() { return sizeof(T) == sizeof(double) ? 2 : 1; }
 
 template <typename T>
 hipError_t launch_mff_left(int n, int N, const T* Pe, const T* Po, const T* B, T* C, int nseg, long seg_stride,
@@ -1135,10 +1150,10 @@ hipError_t launch_mfu_left(int n, int N, const T* Pse, const T* Pso, const T* B,
   const dim3 grid(blocks_for(blocks_for(N, 16 * kMfW), 4));
 #define BODY(RT)                                                                                                   \
   if (lm)                                                                                                          \
-    hipLaunchKernelGGL((k_mfu_left<T, RT, kMfW, true, kMfPD, kMfLBu>), grid, dim3(256), 0, st, n, he, ho, N, Pse, Pso, B, C, nseg,  \
+    hipLaunchKernelGGL((k_mfu_left<T, RT, kMfW, true, kMfPD, mf_lbu<T>()>), grid, dim3(256), 0, st, n, he, ho, N, Pse, Pso, B, C, nseg,  \
                        seg_stride, kstride, lm, ly, lx, nxs, zm, zj, zi);                                          \
   else                                                                                                             \
-    hipLaunchKernelGGL((k_mfu_left<T, RT, kMfW, false, kMfPD, kMfLBu>), grid, dim3(256), 0, st, n, he, ho, N, Pse, Pso, B, C, nseg, \
+    hipLaunchKernelGGL((k_mfu_left<T, RT, kMfW, false, kMfPD, mf_lbu<T>()>), grid, dim3(256), 0, st, n, he, ho, N, Pse, Pso, B, C, nseg, \
                        seg_stride, kstride, lm, ly, lx, nxs, zm, zj, zi);
   LK_MF_SWITCH((he + 15) / 16, BODY)
 #undef BODY
@@ -1159,7 +1174,7 @@ template <typename T>
 hipError_t launch_mfu_right(int n, int Mlines, const T* A, const T* Pse, const T* Pso, T* C, hipStream_t st) {
   const int he = (n + 1) / 2, ho = n / 2;
   const dim3 grid(blocks_for(blocks_for(Mlines, 16 * kMfW), 4));
-#define BODY(RT) hipLaunchKernelGGL((k_mfu_right<T, RT, kMfW, kMfPD, kMfLBu>), grid, dim3(256), 0, st, n, he, ho, Mlines, A, Pse, Pso, C);
+#define BODY(RT) hipLaunchKernelGGL((k_mfu_right<T, RT, kMfW, kMfPD, mf_lbu<T>()>), grid, dim3(256), 0, st, n, he, ho, Mlines, A, Pse, Pso, C);
   LK_MF_SWITCH((he + 15) / 16, BODY)
 #undef BODY
   return hipGetLastError();

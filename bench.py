@@ -44,6 +44,10 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=2, help="oracle Krylov vectors timed on the host")
     ap.add_argument("--train-steps", type=int, default=300, help="Adam steps of the learned guess (64^3 pairs)")
     ap.add_argument("--train-size", type=int, default=64)
+    ap.add_argument("--critical", type=int, default=0, metavar="N",
+                    help="instead of the Krylov-vector benchmark: critical Reynolds number of the N^3 cube "
+                         "on the sine grid of eq. 5, lid along x (Newton continuation, then the secant "
+                         "driver lc_critical_re); one JSON line")
     return ap.parse_args()
 
 
@@ -210,6 +214,52 @@ def cpu_baseline(n, sample):
             "seconds": dt}
 
 
+# Table 3 of the paper (alpha = 0, sine grid of eq. 5): critical Re and frequency per grid
+PAPER_TABLE3_A0 = {100: (1963.74, 0.575370), 150: (1938.98, 0.581315), 200: (1930.40, 0.583398),
+                   256: (1926.10, 0.584438)}
+
+
+def critical_run(n, lk, torch):
+    """Steady states continued from rest up to Re = 1930, then the secant search for the
+    critical Reynolds number (the leading eigenvalue of eq. 7 crossing the imaginary
+    axis) from Re = 1940 and 1990.  The continuation and driver settings were chosen
+    for the 100^3 grid."""
+    ctx = lk.Context(n)
+    ctx.set_stretching("sine", 0.0)
+    ctx.set_lid(0.0)
+    ctx.set_base_flow(torch.zeros(ctx.nvel, dtype=torch.float64, device="cuda"))
+    t0 = time.perf_counter()
+    cont = []
+    for re in (250.0, 500.0, 800.0, 1100.0, 1400.0, 1600.0, 1750.0, 1850.0, 1930.0):
+        ctx.set_re(re)
+        for step in range(9):
+            _, r = ctx.newton_residual()
+            log(f"[critical] Re {re:g} Newton step {step}: |P R(U)| {r:.2e} ({time.perf_counter() - t0:.0f} s)")
+            if r <= 1e-9 or step == 8:
+                break
+            ctx.newton_step(lin_tol=1e-9, gmres_m=100, max_vectors=20000)
+        cont.append({"re": re, "newton_steps": step, "res_inf": r})
+    t1 = time.perf_counter()
+    os.environ["LK_VERBOSE"] = "1"  # progress trace on stderr during the long driver call
+    out = ctx.critical_re(1940.0, 1990.0, re_tol=2e-5, max_evals=5, newton_tol=1e-9, newton_steps=6,
+                          lin_tol=1e-9, gmres_m=100, max_vectors=20000, k=8, m=100, eig_tol=1e-6,
+                          max_restarts=120, seed=1)
+    os.environ["LK_VERBOSE"] = "0"
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    res = {"metric": "critical Reynolds number (leading eigenvalue of eq. 7 crossing the imaginary axis)",
+           "grid": [n, n, n], "stretching": "sine (eq. 5)", "alpha_deg": 0.0, "re_cr": out["re_cr"],
+           "omega_cr": out["omega_cr"], "converged": out["converged"],
+           "evaluations": [{"re": h[0], "re_lambda": h[1], "im_lambda": h[2], "res_inf": h[3]}
+                           for h in out["history"]],
+           "continuation": cont, "seconds_continuation": t1 - t0, "seconds_critical": t2 - t1}
+    if n in PAPER_TABLE3_A0:
+        pre, pom = PAPER_TABLE3_A0[n]
+        res["paper_table3"] = {"re_cr": pre, "omega_cr": pom, "re_rel_diff": out["re_cr"] / pre - 1.0,
+                               "omega_rel_diff": out["omega_cr"] / pom - 1.0}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -218,6 +268,10 @@ def main():
         sys.exit(1)
     import torch
     import paper_1704_08521_amd as lk
+    if a.critical:
+        torch.cuda.set_device(0)
+        critical_run(a.critical, lk, torch)
+        return
     n = a.size
     torch.cuda.set_device(0)
     ctx = lk.Context(n, n, n)

@@ -196,9 +196,12 @@ int lc_newton_step(lc_ctx* ctx, double lin_tol, int gmres_m, long max_vectors, i
  * orthogonalizes by modified Gram-Schmidt in float64 (repeated once when the
  * norm drops below 1/sqrt 2 of its value); the m x m Hessenberg eigenproblem
  * is solved in float64 on the host and the m - k unwanted Ritz values serve as
- * exact shifts (complex pairs as real double shifts).  Ritz values of modulus
- * below 1e-5 of the largest are treated as unwanted (they come from the gradient
- * directions, where P L_U is zero; so are true eigenvalues that small).  Converged when every
+ * exact shifts (complex pairs as real double shifts).  A kept Ritz value of
+ * modulus below 1e-5 of the largest is treated as unwanted when its Ritz vector is
+ * far from divergence-free (relative divergence above 1e-6 of a raw random
+ * vector's): such values come from rounding-level components in the gradient
+ * directions, where P L_U is zero; a genuine eigenvalue near 0 (a real eigenvalue
+ * crossing the imaginary axis) is divergence-free and is kept.  Converged when every
  * wanted pair has |h_{m+1,m} e_m^T y| <= tol |theta|.  If the k-th and (k+1)-th
  * values are a conjugate pair both are returned.
  * Requirements: 1 <= k <= 46, k + 3 <= m <= 100.  Outputs (host): eig_re,
@@ -211,6 +214,43 @@ int lc_newton_step(lc_ctx* ctx, double lin_tol, int gmres_m, long max_vectors, i
 int lc_arnoldi_leading(lc_ctx* ctx, int k, int m, double tol, int max_restarts, unsigned long long seed,
                        int precision, double proj_tol, double* eig_re, double* eig_im, double* resid,
                        double* vec_re, double* vec_im, int* n_out, long* n_vectors);
+
+/* ------------------------------------------------- critical Reynolds number */
+
+/* Options of lc_critical_re. */
+typedef struct {
+  double re_tol;          /* stop when the secant update |dRe| <= re_tol * Re              */
+  int max_evals;          /* steady-state + eigenvalue evaluations (>= 2)                  */
+  double newton_tol;      /* steady state: max |P R(U)| <= newton_tol (lc_newton_residual) */
+  int newton_steps;       /* at most this many Newton steps per evaluation                 */
+  double lin_tol;         /* Newton linear solves, as in lc_newton_step                    */
+  int gmres_m;
+  long max_vectors;
+  int k, m;               /* Arnoldi, as in lc_arnoldi_leading (float64 Krylov vectors)    */
+  double eig_tol;
+  int max_restarts;
+  unsigned long long seed;
+} lc_critical_opts;
+
+/* Critical Reynolds number of the context's grid and lid direction (Section 2, the
+ * paragraph after eq. 7): the Re at which the leading eigenvalue Lambda (largest
+ * real part) of the stability problem crosses the imaginary axis, and the critical
+ * frequency |Im Lambda| there.  The paper does not say how it located the root; this
+ * driver uses the secant method on Re -> Re Lambda(Re) from re0 and re1.  Each
+ * evaluation sets Re, starts from the context's base flow (first evaluation) or from
+ * the linear extrapolation in Re of the last two steady states, runs Newton steps
+ * (lc_newton_step) until max |P R(U)| <= newton_tol or newton_steps, then
+ * lc_arnoldi_leading (LC_ENOTCONV there is accepted: its last Ritz values are used).
+ * The context's base flow should be a steady state (or a good guess) at re0; on
+ * return it holds the last steady state and Re the last evaluated value.
+ * Outputs (host): re_cr, omega_cr (|Im Lambda| interpolated linearly in Re between the
+ * last two evaluations); hist (NULL or 4 * max_evals doubles) rows (Re, Re Lambda,
+ * |Im Lambda|, max |P R(U)| reached); n_evals.  Returns LC_ENOTCONV when max_evals
+ * evaluations did not meet re_tol (outputs then hold the last secant iterate).
+ * Workspace: three velocity vectors (the stored steady states and a residual) plus
+ * those of Newton and Arnoldi (library-owned). */
+int lc_critical_re(lc_ctx* ctx, double re0, double re1, const lc_critical_opts* opt, double* re_cr,
+                   double* omega_cr, double* hist, int* n_evals);
 
 /* ------------------------------------------------- learned correction guess */
 

@@ -10,7 +10,7 @@ import ctypes as C
 import numpy as np
 
 from . import _lib
-from ._lib import FP64, LEARNED, MIXED, SINE, TANH, UNIFORM, LidKrylovError, Stats  # noqa: F401
+from ._lib import FP64, LEARNED, MIXED, SINE, TANH, UNIFORM, CriticalOpts, LidKrylovError, Stats  # noqa: F401
 
 __all__ = ["Context", "Net", "FP64", "MIXED", "LEARNED", "UNIFORM", "SINE", "TANH", "LidKrylovError"]
 
@@ -206,6 +206,22 @@ class Context:
         if vectors:
             out["vectors"] = (vre[:n], vim[:n])
         return out
+
+    def critical_re(self, re0, re1, re_tol=1e-8, max_evals=12, newton_tol=1e-10, newton_steps=12, lin_tol=1e-10,
+                    gmres_m=100, max_vectors=5000, k=6, m=40, eig_tol=1e-10, max_restarts=400, seed=1):
+        """Critical Reynolds number and frequency: secant on the real part of the leading
+        eigenvalue from re0, re1 (the base flow should be a steady state at re0)."""
+        o = CriticalOpts(float(re_tol), int(max_evals), float(newton_tol), int(newton_steps), float(lin_tol),
+                         int(gmres_m), int(max_vectors), int(k), int(m), float(eig_tol), int(max_restarts), int(seed))
+        rc_, om = C.c_double(), C.c_double()
+        ne = C.c_int()
+        hist = np.zeros(4 * max(int(max_evals), 2))
+        rc = self._check(self.lib.lc_critical_re(self._h, float(re0), float(re1), C.byref(o), C.byref(rc_),
+                                                 C.byref(om), hist.ctypes.data_as(C.c_void_p), C.byref(ne)),
+                         allow_notconv=True)
+        n = ne.value
+        return {"re_cr": rc_.value, "omega_cr": om.value, "converged": rc == 0,
+                "history": [tuple(hist[4 * i:4 * i + 4]) for i in range(n)]}
 
     # ----------------------------------------------------------- profiling
     # ------------------------------------------------------ learned guess

@@ -22,6 +22,14 @@ class LidKrylovError(RuntimeError):
         self.code = code
 
 
+class CriticalOpts(C.Structure):
+    """lc_critical_opts (field meaning in include/lidkrylov.h)."""
+    _fields_ = [("re_tol", C.c_double), ("max_evals", C.c_int), ("newton_tol", C.c_double),
+                ("newton_steps", C.c_int), ("lin_tol", C.c_double), ("gmres_m", C.c_int),
+                ("max_vectors", C.c_long), ("k", C.c_int), ("m", C.c_int), ("eig_tol", C.c_double),
+                ("max_restarts", C.c_int), ("seed", C.c_ulonglong)]
+
+
 class Stats(C.Structure):
     _fields_ = [("iterations", C.c_int), ("rho", C.c_double), ("rho0", C.c_double),
                 ("rho_hist", C.c_double * 16), ("ms_total", C.c_double), ("guess_used", C.c_int),
@@ -67,6 +75,8 @@ _SIGS = {
                             C.POINTER(_I)]),
     "lc_arnoldi_leading": (_I, [_P, _I, _I, _D, _I, C.c_ulonglong, _I, _D, _P, _P, _P, _P, _P, C.POINTER(_I),
                                 C.POINTER(C.c_long)]),
+    "lc_critical_re": (_I, [_P, _D, _D, C.POINTER(CriticalOpts), C.POINTER(_D), C.POINTER(_D), _P,
+                            C.POINTER(_I)]),
     "lc_net_param_count": (C.c_long, []),
     "lc_net_create": (_I, [C.POINTER(_P), C.c_uint64]),
     "lc_net_destroy": (_I, [_P]),

@@ -436,7 +436,7 @@ int lc_destroy(lc_ctx* c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   else (void)hipDeviceSynchronize();
   void* ptrs[] = {c->U, c->w, c->r, c->phi, c->t1, c->t2, c->r32, c->t1_32, c->t2_32, c->partials,
-                  c->dsum, c->metric, c->modes_mem, c->dsmall, c->pk, c->kws};
+                  c->dsum, c->metric, c->modes_mem, c->dsmall, c->pk, c->kws, c->ucr};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (c->hsum) (void)hipHostFree(c->hsum);

@@ -94,6 +94,7 @@ struct lc_ctx {
   double* dsmall = nullptr;  // kSmall doubles
   double* hsmall = nullptr;  // kSmall doubles, pinned
   double* pk = nullptr;      // cell
+  double* ucr = nullptr;     // critical-Re driver: two stored steady states + a residual
   lc_net* net = nullptr;     // learned guess (not owned)
   bool prof = false;
   std::vector<Rec> recs;

@@ -53,12 +53,9 @@ struct KMap {
 
 // out = P L_U in (one Krylov vector); a projection that misses its tolerance is
 // an error here (the Krylov drivers need the divergence-free subspace).
-bool verbose() {
-  static const bool v = [] {
-    const char* e = std::getenv("LK_VERBOSE");
-    return e && e[0] && e[0] != '0';
-  }();
-  return v;
+bool verbose() {  // read on every call: callers may switch the trace on around one driver call
+  const char* e = std::getenv("LK_VERBOSE");
+  return e && e[0] && e[0] != '0';
 }
 
 int kmap(lc_ctx* c, KMap& K, const double* in, double* out) {
@@ -174,6 +171,13 @@ extern "C" int lc_arnoldi_leading(lc_ctx* c, int k, int m, double tol, int max_r
   // start vector: seeded uniform [-1, 1), projected onto the divergence-free space
   KLAUNCH(c, LC_K_VECTOR, launch_uniform(W.at(0), c->nvel, seed, c->stream));
   KLAUNCH(c, LC_K_VECTOR, launch_zero_walls(W.at(0), c->nx, c->ny, c->nz, c->stream));
+  // divergence scale of a vector with no solenoidal structure (the raw start vector):
+  // a Ritz vector whose relative divergence is a sizeable fraction of it is not an
+  // eigenvector of eq. 7 (see `spurious` below)
+  double dref = 0.0, wn = 0.0;
+  if ((rc = vnorm_div(c, W.at(0), nullptr, &dref))) return rc;
+  if ((rc = vdot(c, W.at(0), W.at(0), &wn))) return rc;
+  dref /= std::max(vnorm(wn), 1e-300);
   lc_stats st;
   rc = lc_project(c, W.at(0), V.at(0), c->pk, LC_FP64, 1e-13, 4, &st);
   if (rc < 0) return rc;
@@ -211,14 +215,48 @@ extern "C" int lc_arnoldi_leading(lc_ctx* c, int k, int m, double tol, int max_r
     // P L_U is zero on the gradient directions, to the right of the wanted
     // eigenvalues; rounding-level components there grow under the restart filter
     // and show up as Ritz values near 0.  Sorting those among the unwanted makes
-    // them exact shifts, which removes them when (and only when) they appear.
-    auto spurious = [&](const cplx& t) { return std::abs(t) < 1e-5 * tmax; };
-    std::stable_sort(theta.begin(), theta.end(), [&](const cplx& a, const cplx& b) {
-      const bool sa = spurious(a), sb = spurious(b);
-      if (sa != sb) return sb;
+    // them exact shifts, which removes them when (and only when) they appear.  A
+    // genuine eigenvalue can be near 0 too (a real eigenvalue crossing the imaginary
+    // axis), so a near-zero Ritz value that would be kept is judged by its Ritz
+    // vector: spurious when that vector is far from divergence-free.
+    auto by_real = [](const cplx& a, const cplx& b) {
       if (a.real() != b.real()) return a.real() > b.real();
       return a.imag() > b.imag();
-    });
+    };
+    std::stable_sort(theta.begin(), theta.end(), by_real);
+    std::vector<char> spur(m, 0);
+    const int front = std::min(m, k + std::max(1, (m - k) / 3) + 2);
+    for (int i = 0; i < front; ++i) {
+      if (!(std::abs(theta[i]) < 1e-5 * tmax)) continue;
+      std::vector<cplx> y;
+      if (!hess_eigvec(m, Hm, theta[i], y)) return fail(c, LC_EINVAL, "Ritz vector failed");
+      std::vector<double> Qy((size_t)m * 2);
+      for (int r = 0; r < m; ++r) {
+        Qy[(size_t)r * 2] = y[r].real();
+        Qy[(size_t)r * 2 + 1] = y[r].imag();
+      }
+      std::memcpy(c->hsmall, Qy.data(), Qy.size() * sizeof(double));
+      HIPCHK(c, hipMemcpyAsync(c->dsmall, c->hsmall, Qy.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+      KLAUNCH(c, LC_K_VECTOR, launch_combine(V.p, V.ld, m, c->dsmall, 2, W.p, W.ld, c->nvel, c->stream));
+      double d0 = 0.0, d1 = 0.0, n0 = 0.0, n1 = 0.0;
+      if ((rc = vnorm_div(c, W.at(0), nullptr, &d0)) || (rc = vnorm_div(c, W.at(1), nullptr, &d1)) ||
+          (rc = vdot(c, W.at(0), W.at(0), &n0)) || (rc = vdot(c, W.at(1), W.at(1), &n1)))
+        return rc;
+      const double rel = std::hypot(d0, d1) / std::max(vnorm(n0 + n1), 1e-300) / std::max(dref, 1e-300);
+      spur[i] = rel > 1e-6;
+      if (verbose())
+        std::fprintf(stderr, "[lk arnoldi] near-zero Ritz value %.3e%+.3ei: relative divergence %.2e (%s)\n",
+                     theta[i].real(), theta[i].imag(), rel, spur[i] ? "spurious" : "kept");
+    }
+    {
+      std::vector<std::pair<cplx, char>> tv(m);
+      for (int i = 0; i < m; ++i) tv[i] = {theta[i], spur[i]};
+      std::stable_sort(tv.begin(), tv.end(), [&](const std::pair<cplx, char>& a, const std::pair<cplx, char>& b) {
+        if (a.second != b.second) return b.second != 0;
+        return by_real(a.first, b.first);
+      });
+      for (int i = 0; i < m; ++i) theta[i] = tv[i].first;
+    }
     for (int i = 0; i + 1 < m; ++i)  // within a conjugate pair: positive imaginary part first
       if (is_pair(theta[i], theta[i + 1])) {
         if (theta[i].imag() < theta[i + 1].imag()) std::swap(theta[i], theta[i + 1]);
@@ -537,4 +575,99 @@ extern "C" int lc_newton_step(lc_ctx* c, double lin_tol, int gmres_m, long max_v
   if (corr_inf) *corr_inf = cinf;
   if (n_vectors) *n_vectors = K.count;
   return solved ? LC_OK : LC_ENOTCONV;
+}
+
+// ================================================================ critical Reynolds number
+extern "C" int lc_critical_re(lc_ctx* c, double re0, double re1, const lc_critical_opts* o, double* re_cr,
+                              double* omega_cr, double* hist, int* n_evals) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  if (!o || !re_cr || !omega_cr || !n_evals) return fail(c, LC_EINVAL, "null argument");
+  if (!(re0 > 0.0) || !(re1 > 0.0) || re0 == re1 || !std::isfinite(re0) || !std::isfinite(re1))
+    return fail(c, LC_EINVAL, "need two distinct positive starting Reynolds numbers");
+  if (o->max_evals < 2 || o->newton_steps < 0 || !(o->re_tol > 0.0) || !(o->newton_tol > 0.0))
+    return fail(c, LC_EINVAL, "bad critical-Re options");
+  *n_evals = 0;
+  if (!c->ucr && hipMalloc((void**)&c->ucr, 3 * c->nvel * sizeof(double)) != hipSuccess)
+    return fail(c, LC_ENOMEM, "cannot allocate the stored steady states");
+  double* Us[2] = {c->ucr, c->ucr + c->nvel};  // the last two steady states, oldest first
+  double* Fr = c->ucr + 2 * c->nvel;            // projected residual (scratch)
+  double Re_s[2] = {0.0, 0.0};
+  int nstored = 0;
+  std::vector<double> R, F, W;  // evaluations: Re, Re Lambda, |Im Lambda|
+  const int kk = std::max(o->k, 1);
+  std::vector<double> er(kk + 1), ei(kk + 1), res(kk + 1);
+  auto evaluate = [&](double re) -> int {
+    if (nstored == 2) {  // U = U_b + (U_b - U_a) (re - re_b) / (re_b - re_a)
+      const double t = (re - Re_s[1]) / (Re_s[1] - Re_s[0]);
+      int r2;
+      if ((r2 = vcopy(c, Us[1], c->U))) return r2;
+      if ((r2 = vscale(c, 1.0 + t, c->U))) return r2;
+      if ((r2 = vaxpy(c, -t, Us[0], c->U))) return r2;
+    } else if (nstored == 1) {
+      int r2;
+      if ((r2 = vcopy(c, Us[1], c->U))) return r2;
+    }
+    c->re = re;
+    double rinf = 0.0;
+    int r2;
+    for (int s = 0;; ++s) {
+      if ((r2 = lc_newton_residual(c, Fr, &rinf))) return r2;
+      if (rinf <= o->newton_tol || s >= o->newton_steps) break;
+      double ri, ci;
+      long nv;
+      int bi;
+      r2 = lc_newton_step(c, o->lin_tol, o->gmres_m, o->max_vectors, LC_FP64, 1e-12, &ri, &ci, &nv, &bi);
+      if (r2 < 0) return r2;
+    }
+    // keep this steady state (oldest dropped)
+    std::swap(Us[0], Us[1]);
+    Re_s[0] = Re_s[1];
+    if ((r2 = vcopy(c, c->U, Us[1]))) return r2;
+    Re_s[1] = re;
+    nstored = std::min(nstored + 1, 2);
+    int nout = 0;
+    long nvec = 0;
+    r2 = lc_arnoldi_leading(c, o->k, o->m, o->eig_tol, o->max_restarts, o->seed, LC_FP64, 1e-12, er.data(),
+                            ei.data(), res.data(), nullptr, nullptr, &nout, &nvec);
+    if (r2 < 0) return r2;
+    if (nout < 1) return fail(c, LC_ENOTCONV, "no Ritz values at Re = %g", re);
+    int lead = 0;
+    for (int i = 1; i < nout; ++i)
+      if (er[i] > er[lead]) lead = i;
+    if (hist && (int)R.size() < o->max_evals) {
+      double* h = hist + 4 * R.size();
+      h[0] = re;
+      h[1] = er[lead];
+      h[2] = std::fabs(ei[lead]);
+      h[3] = rinf;
+    }
+    R.push_back(re);
+    F.push_back(er[lead]);
+    W.push_back(std::fabs(ei[lead]));
+    *n_evals = (int)R.size();
+    if (verbose())
+      std::fprintf(stderr, "[lk critical] Re %.8f: Lambda %+.10e %+.10ei, |F| %.2e\n", re, er[lead], ei[lead], rinf);
+    return LC_OK;
+  };
+  if ((rc = evaluate(re0))) return rc;
+  if ((rc = evaluate(re1))) return rc;
+  bool converged = false;
+  double rn = R.back();
+  while (true) {
+    const size_t b = R.size() - 1, a = b - 1;
+    if (F[b] == F[a]) break;
+    rn = R[b] - F[b] * (R[b] - R[a]) / (F[b] - F[a]);
+    if (!std::isfinite(rn) || !(rn > 0.0)) return fail(c, LC_ENOTCONV, "secant left the positive axis");
+    if (std::fabs(rn - R[b]) <= o->re_tol * std::fabs(R[b])) {
+      converged = true;
+      break;
+    }
+    if ((int)R.size() >= o->max_evals) break;
+    if ((rc = evaluate(rn))) return rc;
+  }
+  const size_t b = R.size() - 1, a = b - 1;
+  *re_cr = rn;
+  *omega_cr = W[b] + (W[b] - W[a]) * (rn - R[b]) / (R[b] - R[a]);
+  return converged ? LC_OK : LC_ENOTCONV;
 }

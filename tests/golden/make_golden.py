@@ -9,7 +9,15 @@
 * ``leading_16_uniform_re100_a0.txt``: the six leading eigenvalues of the 16^3
   uniform cube, Re = 100, alpha = 0 (the first workload: Newton, then Arnoldi
   for the leading eigenvalues), from ARPACK on the oracle's Krylov map.
+* ``critical_16_sine_a45.txt``: the critical Reynolds number and frequency of the
+  16^3 cube on the sine-stretched grid of eq. 5 with the lid along the diagonal
+  (alpha = 45 deg) (oracle.critical: secant on Re Lambda from Re = 2300 and 2500,
+  steady states continued from Re = 500).  On this coarse grid a complex pair crosses
+  first (a Hopf crossing, as in the paper's cube, though at a grid-scale frequency).
+
+``python tests/golden/make_golden.py critical`` rewrites the last file only.
 """
+import math
 import os
 import sys
 
@@ -18,6 +26,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
+from oracle import critical as crit  # noqa: E402
 from oracle import eigen  # noqa: E402
 from oracle.grid import Grid  # noqa: E402
 from oracle.newton import Newton  # noqa: E402
@@ -56,5 +65,31 @@ def main():
            "(largest real part) from ARPACK on the oracle's Krylov-vector map")
 
 
+def critical():
+    g = Grid.make(16, kind="sine")
+    alpha = math.radians(45.0)
+    U = None
+    for re in (500.0, 1000.0, 1500.0, 2000.0, 2300.0):
+        U, hist = Newton(g, re, alpha).solve(U, tol=1e-11, max_steps=30)
+        print(f"16^3 sine alpha 45 Re {re}: Newton |F| {hist[-1]:.1e} after {len(hist)}", flush=True)
+    out = crit.critical_re(g, 2300.0, 2500.0, U, alpha=alpha, re_tol=1e-9, max_evals=14, newton_tol=1e-11)
+    assert out["converged"], out
+    path = os.path.join(HERE, "critical_16_sine_a45.txt")
+    with open(path, "w") as f:
+        f.write("# 16^3 cube, sine-stretched grid (eq. 5), lid along the diagonal (alpha = 45 deg):\n"
+                "# critical Reynolds number and frequency from oracle.critical (secant on Re Lambda\n"
+                "# from Re = 2300, 2500; Newton steady states continued from Re = 500 through 1000,\n"
+                "# 1500, 2000)\n")
+        f.write(f"re_cr {out['re_cr']:.12f}\nomega_cr {out['omega_cr']:.12f}\n")
+        f.write("# evaluations: Re, Re Lambda, Im Lambda\n")
+        for re, lr, li in out["history"]:
+            f.write(f"# {re:.10f} {lr:+.12e} {li:+.12e}\n")
+    print("wrote", path, out["re_cr"], out["omega_cr"], flush=True)
+
+
 if __name__ == "__main__":
-    main()
+    if sys.argv[1:] == ["critical"]:
+        critical()
+    else:
+        main()
+        critical()

@@ -1,0 +1,97 @@
+"""Pins of the critical-Reynolds-number oracle (oracle.critical).
+
+Richardson extrapolation against every extrapolated value the paper prints (Tables 2
+and 3, tests/golden/paper_critical_tables.txt) and against its closed form; the secant
+search against synthetic leading eigenvalues whose crossing is known in closed form
+(the steady-state solver replaced by a stub, so only the driver's own arithmetic is
+exercised); the steady-state predictor against exact linear data.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import critical as crit
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def paper_rows():
+    rows = []
+    for line in open(os.path.join(HERE, "golden", "paper_critical_tables.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        t, case, n, re, om, rex, omx = line.split()
+        rows.append((t, case, int(n), float(re), float(om), None if rex == "-" else float(rex),
+                     None if omx == "-" else float(omx)))
+    return rows
+
+
+def test_richardson_reproduces_the_papers_extrapolations():
+    rows = paper_rows()
+    checked = 0
+    for prev, cur in zip(rows, rows[1:]):
+        if prev[1] != cur[1] or cur[5] is None:
+            continue
+        re_x = crit.richardson(prev[2], prev[3], cur[2], cur[3])
+        om_x = crit.richardson(prev[2], prev[4], cur[2], cur[4])
+        # the extrapolations are printed to 2-3 decimals (Re) and 5-6 significant digits
+        # (omega), apparently from unrounded grid values (alpha = 0, 150^3: 1919.172 from
+        # the printed inputs, 1919.16 printed); one entry of Table 3 (alpha = 0, 256^3:
+        # 1926.10 after 1930.40 extrapolates to 1919.34, the table prints 1919.37) is
+        # inconsistent with its own inputs by 0.03
+        tol_re = 0.05 if (cur[1], cur[2]) == ("a0", 256) else 0.015
+        assert abs(re_x - cur[5]) <= tol_re, (cur, re_x)
+        assert abs(om_x - cur[6]) <= 1.1e-5, (cur, om_x)
+        checked += 1
+    assert checked == 11
+
+
+def test_richardson_closed_form():
+    # v(N) = v0 + c / N^2 is extrapolated exactly; a first-order error is not
+    v = lambda n: 7.25 + 3.0 / n ** 2
+    assert crit.richardson(100, v(100), 150, v(150)) == pytest.approx(7.25, abs=1e-13)
+    w = lambda n: 7.25 + 3.0 / n
+    assert abs(crit.richardson(100, w(100), 150, w(150)) - 7.25) > 1e-3
+    assert crit.richardson(100, w(100), 150, w(150), order=1) == pytest.approx(7.25, abs=1e-13)
+
+
+def test_secant_step_solves_linear_functions_exactly():
+    f = lambda x: 2.0 * x - 3.0
+    assert crit.secant_step(0.0, f(0.0), 10.0, f(10.0)) == pytest.approx(1.5, abs=1e-14)
+
+
+def test_predictor_extrapolates_linearly():
+    a, b = np.arange(5.0), np.arange(5.0) * 3.0 + 1.0
+    assert np.array_equal(crit.predict([(10.0, a)], 20.0), a)
+    got = crit.predict([(10.0, a), (20.0, b)], 35.0)
+    assert np.allclose(got, b + (b - a) * 1.5, rtol=0, atol=1e-14)
+
+
+class _StubNewton:
+    """Stands in for the steady-state solver: returns its initial guess."""
+    def __init__(self, g, re, alpha):
+        pass
+
+    def solve(self, U0=None, tol=None, max_steps=None):
+        return (np.zeros(3) if U0 is None else U0), [0.0]
+
+
+@pytest.mark.parametrize("kind", ["linear", "tanh"])
+def test_secant_search_finds_known_crossings(monkeypatch, kind):
+    monkeypatch.setattr(crit, "Newton", _StubNewton)
+    if kind == "linear":
+        lam = lambda re: complex((re - 1234.5) / 1000.0, 0.3)
+        root, omega = 1234.5, 0.3
+    else:  # Re Lambda = tanh((Re - 1500) / 300) - 0.2, Im Lambda linear in Re
+        lam = lambda re: complex(math.tanh((re - 1500.0) / 300.0) - 0.2, 0.5 + 1e-4 * (re - 1500.0))
+        root = 1500.0 + 300.0 * math.atanh(0.2)
+        omega = 0.5 + 1e-4 * (root - 1500.0)
+    out = crit.critical_re(None, 1400.0, 1700.0, np.zeros(3), re_tol=1e-12, max_evals=30,
+                           leading_fn=lambda g, U, re: lam(re))
+    assert out["converged"]
+    assert out["re_cr"] == pytest.approx(root, rel=1e-11)
+    assert out["omega_cr"] == pytest.approx(omega, abs=1e-10)
+    if kind == "linear":
+        assert len(out["history"]) == 3  # two starts and one exact secant step

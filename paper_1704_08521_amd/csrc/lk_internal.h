@@ -127,7 +127,7 @@ hipError_t launch_tpu_right(int n, int Mlines, const T* A, const T* SeT, const T
 // lx, zero mode) belongs to the backward left transform: its input modes are scaled on
 // load.
 constexpr int kMfMaxHalf = 128;
-constexpr int kMfPD = 2;
+constexpr int kMfPD = 1;
 __host__ __device__ constexpr int mf_steps(int he, int pd = kMfPD) { return ((he + 3) / 4 + pd - 1) / pd * pd; }
 // Fragments are grouped fg = 16 / sizeof(element) per lane (one 16-byte load fetches fg
 // consecutive row tiles): fragment (kq, t, lane) sits at mf_pack_index(kq, t, lane, RT, fg).

@@ -715,7 +715,8 @@ __device__ __forceinline__ void mf_fold(const bool (&ok)[W], int n, int he, int 
 // Accumulates the even and odd contractions of one wave: acc_e += Pe x s, acc_o += Po x d
 // over the KQP steps of the (padded) packs.  Vector-memory loads complete in issue order,
 // so every load of a step - raw data (HBM), pack fragments (L1/L2) and eigenvalues alike -
-// is issued PD steps ahead into a register ring; the step loop has no conditional exits
+// is issued PD steps ahead into a register ring (PD = 1 in use: the registers a deeper
+// ring costs buy more as a third wave per SIMD); the step loop has no conditional exits
 // (KQP is a multiple of PD, the padding steps hold zero fragments and masked data), which
 // lets the compiler wait for exactly the oldest step's loads instead of draining all of
 // them at the loop head.  LEFT: the pack is the A operand; otherwise the data is.
@@ -1123,19 +1124,21 @@ LK_TPF_INST(float)
     case 8: BODY(8) break;      \
     default: return hipErrorInvalidValue; \
   }
-// forward kernels keep their accumulators in AGPRs at 2 waves per SIMD by themselves;
-// the FP64 backward ones (a + b, a - b epilogue) need the 2-wave bound to get there (the
-// FP32 ones reach 5-6 waves unbounded and run slower bounded)
-constexpr int kMfW = 1, kMfLBf = 1;
-template <typename T>
-constexpr int mf_lbu() { return sizeof(T) == sizeof(double) ? 2 : 1; }
+// Waves per SIMD: a 200^3 transform is 2500 waves, and at 2 per SIMD (2048 slots) the
+// last 452 form a second round that costs half the kernel time (measured: 40 us for 2048
+// waves, 60 us for 2304..2500).  With a one-step prefetch ring the FP64 kernels fit 3 per
+// SIMD (168 registers) and all 2500 waves run in one round (51-57 us); the FP32 ones do
+// best at 2, and so do FP64 kernels with 8 row tiles (n > 224), which spill at 3.
+constexpr int kMfW = 1;
+template <typename T, int RT>
+constexpr int mf_lb() { return sizeof(T) == sizeof(double) && RT < 8 ? 3 : 2; }
 
 template <typename T>
 hipError_t launch_mff_left(int n, int N, const T* Pe, const T* Po, const T* B, T* C, int nseg, long seg_stride,
                            long kstride, hipStream_t st) {
   const int he = (n + 1) / 2, ho = n / 2;
   const dim3 grid(blocks_for(blocks_for(N, 16 * kMfW), 4));
-#define BODY(RT) hipLaunchKernelGGL((k_mff_left<T, RT, kMfW, kMfPD, kMfLBf>), grid, dim3(256), 0, st, n, he, ho, N, Pe, Po, B, C, nseg, \
+#define BODY(RT) hipLaunchKernelGGL((k_mff_left<T, RT, kMfW, kMfPD, mf_lb<T, RT>()>), grid, dim3(256), 0, st, n, he, ho, N, Pe, Po, B, C, nseg, \
                                     seg_stride, kstride);
   LK_MF_SWITCH((he + 15) / 16, BODY)
 #undef BODY
@@ -1150,10 +1153,10 @@ hipError_t launch_mfu_left(int n, int N, const T* Pse, const T* Pso, const T* B,
   const dim3 grid(blocks_for(blocks_for(N, 16 * kMfW), 4));
 #define BODY(RT)                                                                                                   \
   if (lm)                                                                                                          \
-    hipLaunchKernelGGL((k_mfu_left<T, RT, kMfW, true, kMfPD, mf_lbu<T>()>), grid, dim3(256), 0, st, n, he, ho, N, Pse, Pso, B, C, nseg,  \
+    hipLaunchKernelGGL((k_mfu_left<T, RT, kMfW, true, kMfPD, mf_lb<T, RT>()>), grid, dim3(256), 0, st, n, he, ho, N, Pse, Pso, B, C, nseg,  \
                        seg_stride, kstride, lm, ly, lx, nxs, zm, zj, zi);                                          \
   else                                                                                                             \
-    hipLaunchKernelGGL((k_mfu_left<T, RT, kMfW, false, kMfPD, mf_lbu<T>()>), grid, dim3(256), 0, st, n, he, ho, N, Pse, Pso, B, C, nseg, \
+    hipLaunchKernelGGL((k_mfu_left<T, RT, kMfW, false, kMfPD, mf_lb<T, RT>()>), grid, dim3(256), 0, st, n, he, ho, N, Pse, Pso, B, C, nseg, \
                        seg_stride, kstride, lm, ly, lx, nxs, zm, zj, zi);
   LK_MF_SWITCH((he + 15) / 16, BODY)
 #undef BODY
@@ -1164,7 +1167,7 @@ template <typename T>
 hipError_t launch_mff_right(int n, int Mlines, const T* A, const T* Pe, const T* Po, T* C, hipStream_t st) {
   const int he = (n + 1) / 2, ho = n / 2;
   const dim3 grid(blocks_for(blocks_for(Mlines, 16 * kMfW), 4));
-#define BODY(RT) hipLaunchKernelGGL((k_mff_right<T, RT, kMfW, kMfPD, kMfLBf>), grid, dim3(256), 0, st, n, he, ho, Mlines, A, Pe, Po, C);
+#define BODY(RT) hipLaunchKernelGGL((k_mff_right<T, RT, kMfW, kMfPD, mf_lb<T, RT>()>), grid, dim3(256), 0, st, n, he, ho, Mlines, A, Pe, Po, C);
   LK_MF_SWITCH((he + 15) / 16, BODY)
 #undef BODY
   return hipGetLastError();
@@ -1174,7 +1177,7 @@ template <typename T>
 hipError_t launch_mfu_right(int n, int Mlines, const T* A, const T* Pse, const T* Pso, T* C, hipStream_t st) {
   const int he = (n + 1) / 2, ho = n / 2;
   const dim3 grid(blocks_for(blocks_for(Mlines, 16 * kMfW), 4));
-#define BODY(RT) hipLaunchKernelGGL((k_mfu_right<T, RT, kMfW, kMfPD, mf_lbu<T>()>), grid, dim3(256), 0, st, n, he, ho, Mlines, A, Pse, Pso, C);
+#define BODY(RT) hipLaunchKernelGGL((k_mfu_right<T, RT, kMfW, kMfPD, mf_lb<T, RT>()>), grid, dim3(256), 0, st, n, he, ho, Mlines, A, Pse, Pso, C);
   LK_MF_SWITCH((he + 15) / 16, BODY)
 #undef BODY
   return hipGetLastError();

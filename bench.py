@@ -175,7 +175,7 @@ def profile_traffic(cls, n):
 
 
 def time_arnoldi(ctx, lk, torch, m=30, k=6):
-    """Arnoldi extension steps (Krylov vector + FP64 modified Gram-Schmidt) per second:
+    """Arnoldi extension steps (Krylov vector + FP64 Gram-Schmidt) per second:
     one implicitly restarted Arnoldi cycle (m vectors, one restart) on the benchmark
     context; convergence is not the point here."""
     torch.cuda.synchronize()

@@ -174,9 +174,10 @@ int lc_newton_residual(lc_ctx* ctx, double* F, double* res_inf);
 
 /* One Newton step of Section 3 on the context's base flow U: F = P R(U), solve
  * the Jacobian system (P L_U) d = F on the divergence-free space with restarted
- * GMRES(gmres_m) on SIMPLE-evaluated Krylov vectors (modified Gram-Schmidt,
- * float64); a restart that lowers the residual by less than 10% counts as
- * saturation and hands its iterate to BiCGstab(2) (gmres_m = 0: BiCGstab(2)
+ * GMRES(gmres_m) on SIMPLE-evaluated Krylov vectors (classical Gram-Schmidt in
+ * float64, repeated when the norm drops); a restart that lowers the residual by
+ * less than 10% counts as saturation and hands its iterate to BiCGstab(2)
+ * (gmres_m = 0: BiCGstab(2)
  * alone, as Section 3 used it at 100^3); then U <- U - d (step 4).  A saturated
  * restart whose residual is already within sqrt(lin_tol) |F| (the rounding
  * floor of late Newton steps) is accepted as converged.
@@ -193,7 +194,7 @@ int lc_newton_step(lc_ctx* ctx, double lin_tol, int gmres_m, long max_vectors, i
  * P L_U with largest real part, by implicitly restarted Arnoldi on
  * SIMPLE-evaluated Krylov vectors started from a seeded (SplitMix64, `seed`)
  * random vector projected onto the divergence-free space.  Each extension
- * orthogonalizes by modified Gram-Schmidt in float64 (repeated once when the
+ * orthogonalizes by classical Gram-Schmidt in float64 (repeated once when the
  * norm drops below 1/sqrt 2 of its value); the m x m Hessenberg eigenproblem
  * is solved in float64 on the host and the m - k unwanted Ritz values serve as
  * exact shifts (complex pairs as real double shifts).  A kept Ritz value of

@@ -399,7 +399,7 @@ int lc_create(lc_ctx** out, int nx, int ny, int nz, void* hip_stream) {
   c->stream = (hipStream_t)hip_stream;
   c->nvel = vel_layout(nx, ny, nz).total();
   c->ncell = (size_t)nx * ny * nz;
-  c->max_parts = (int)((c->ncell + kReduceBlock - 1) / kReduceBlock) + 4096;
+  c->max_parts = (int)((c->ncell + kReduceBlock - 1) / kReduceBlock) + kGsBlocks * kGsChunk;
   {  // the divergence kernel: 64 x 4 cells x 4 planes per block
     const size_t nd = (size_t)((nx + 63) / 64) * ((ny + 3) / 4) * ((nz + 3) / 4);
     if (nd > (size_t)c->max_parts) c->max_parts = (int)nd;

@@ -71,10 +71,6 @@ hipError_t launch_dot_partials(const double* a, const double* b, size_t n, doubl
 hipError_t launch_max(const double* partials, int n, double* out, hipStream_t st);
 hipError_t launch_maxabs_partials(const double* a, size_t n, double* partials, int* nparts, hipStream_t st);
 
-// Modified Gram-Schmidt step: w -= sign*h[0] * vi (h in device memory); if next is
-// set, per-block partials of next . w_new.
-hipError_t launch_mgs(double* w, const double* vi, const double* next, const double* h, double sign, size_t n,
-                      double* partials, int* nparts, hipStream_t st);
 
 // y += sign * a_dev[0] / d_dev[0] * x (d_dev may be null): scalars from device memory.
 hipError_t launch_axpy_dev(size_t n, const double* a_dev, const double* d_dev, double sign, const double* x,
@@ -162,5 +158,11 @@ hipError_t launch_uniform(double* x, size_t n, uint64_t seed, hipStream_t st);
 hipError_t launch_zero_walls(double* vel, int nx, int ny, int nz, hipStream_t st);
 
 constexpr int kReduceBlock = 256;
+// Classical Gram-Schmidt: h[i] = V_i . w (i < nv; basis vectors ld apart; h on the device,
+// fixed-order sums), then w -= sum_i h[i] V_i.  partials holds kGsBlocks * kGsChunk doubles.
+constexpr int kGsBlocks = 2048, kGsChunk = 8;
+hipError_t launch_gs_dot(const double* V, long ld, int nv, const double* w, size_t n, double* partials,
+                         double* h, hipStream_t st);
+hipError_t launch_gs_update(const double* V, long ld, int nv, const double* h, double* w, size_t n, hipStream_t st);
 
 }  // namespace lk

@@ -118,25 +118,6 @@ __global__ void __launch_bounds__(kReduceBlock) k_maxabs(const double* __restric
   if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
 
-// One modified Gram-Schmidt update with the coefficient read from device memory:
-// w -= h * v_i, and (if next) partial sums of next . w_new for the following step.
-__global__ void __launch_bounds__(kReduceBlock) k_mgs(double* __restrict__ w, const double* __restrict__ vi,
-                                                      const double* __restrict__ next, const double* __restrict__ h,
-                                                      double sign, size_t n, double* __restrict__ partials) {
-  const double c = sign * h[0];
-  double t = 0.0;
-  const size_t stride = (size_t)gridDim.x * blockDim.x;
-  for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) {
-    const double x = w[q] - c * vi[q];
-    w[q] = x;
-    if (next) t += next[q] * x;
-  }
-  if (next) {
-    t = block_sum(t);
-    if (threadIdx.x == 0) partials[blockIdx.x] = t;
-  }
-}
-
 // y = a * x + y with a = sign * (*a_dev) / (*d_dev) read from device memory (d_dev may be null).
 __global__ void k_axpy_dev(size_t n, const double* __restrict__ a_dev, const double* __restrict__ d_dev,
                            double sign, const double* __restrict__ x, double* __restrict__ y) {
@@ -166,6 +147,58 @@ __global__ void __launch_bounds__(256) k_combine(const double* __restrict__ V, l
     if (c < nc) out[(size_t)c * ldo + q] = acc[c];
 }
 
+// Classical Gram-Schmidt in two streaming passes.  Block dot products of NB basis
+// vectors with w (w read once per NB vectors): per-block partial sums, stored
+// partials[i * nblocks + block] for vector i of the chunk.
+template <int NB>
+__global__ void __launch_bounds__(kReduceBlock) k_block_dot(const double* __restrict__ V, long ld, int cnt,
+                                                            const double* __restrict__ w, size_t n,
+                                                            double* __restrict__ partials) {
+  double t[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) t[i] = 0.0;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) {
+    const double x = w[q];
+#pragma unroll
+    for (int i = 0; i < NB; ++i)
+      if (i < cnt) t[i] = fma(V[(size_t)i * ld + q], x, t[i]);
+  }
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    if (i >= cnt) break;
+    const double s = block_sum(t[i]);
+    if (threadIdx.x == 0) partials[(size_t)i * gridDim.x + blockIdx.x] = s;
+    __syncthreads();  // block_sum's shared scratch is reused by the next sum
+  }
+}
+
+// out[b] = fixed-order sum of partials[b * seg .. b * seg + seg) (one block per segment)
+__global__ void __launch_bounds__(1024) k_sum_segments(const double* __restrict__ partials, int seg,
+                                                       double* __restrict__ out) {
+  __shared__ double sh[1024];
+  const double* p = partials + (size_t)blockIdx.x * seg;
+  double t = 0.0;
+  for (int q = threadIdx.x; q < seg; q += 1024) t += p[q];
+  sh[threadIdx.x] = t;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = sh[0];
+}
+
+// w -= sum_i h[i] V[i] (i < nv, coefficients from device memory, summed in order i)
+__global__ void __launch_bounds__(256) k_gs_update(const double* __restrict__ V, long ld, int nv,
+                                                   const double* __restrict__ h, double* __restrict__ w, size_t n) {
+  const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  double acc = 0.0;
+  for (int i = 0; i < nv; ++i) acc = fma(V[(size_t)i * ld + q], h[i], acc);
+  w[q] -= acc;
+}
+
 }  // namespace
 
 hipError_t launch_max(const double* partials, int n, double* out, hipStream_t st) {
@@ -178,15 +211,6 @@ hipError_t launch_maxabs_partials(const double* a, size_t n, double* partials, i
   if (nb > 4096) nb = 4096;
   if (nparts) *nparts = (int)nb;
   hipLaunchKernelGGL(k_maxabs, dim3(nb), dim3(kReduceBlock), 0, st, a, n, partials);
-  return hipGetLastError();
-}
-
-hipError_t launch_mgs(double* w, const double* vi, const double* next, const double* h, double sign, size_t n,
-                      double* partials, int* nparts, hipStream_t st) {
-  unsigned nb = blocks_for(n, kReduceBlock);
-  if (nb > 4096) nb = 4096;
-  if (nparts) *nparts = (int)nb;
-  hipLaunchKernelGGL(k_mgs, dim3(nb), dim3(kReduceBlock), 0, st, w, vi, next, h, sign, n, partials);
   return hipGetLastError();
 }
 
@@ -205,6 +229,24 @@ hipError_t launch_combine(const double* V, long ld, int nv, const double* Q, int
   else if (nc <= 24) hipLaunchKernelGGL(k_combine<24>, grid, block, 0, st, V, ld, nv, Q, nc, out, ldo, n);
   else if (nc <= 48) hipLaunchKernelGGL(k_combine<48>, grid, block, 0, st, V, ld, nv, Q, nc, out, ldo, n);
   else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_gs_dot(const double* V, long ld, int nv, const double* w, size_t n, double* partials,
+                         double* h, hipStream_t st) {
+  unsigned nb = blocks_for(n, kReduceBlock);
+  if (nb > (unsigned)kGsBlocks) nb = kGsBlocks;
+  for (int i0 = 0; i0 < nv; i0 += kGsChunk) {
+    const int cnt = nv - i0 < kGsChunk ? nv - i0 : kGsChunk;
+    hipLaunchKernelGGL(k_block_dot<kGsChunk>, dim3(nb), dim3(kReduceBlock), 0, st, V + (size_t)i0 * ld, ld, cnt, w,
+                       n, partials);
+    hipLaunchKernelGGL(k_sum_segments, dim3(cnt), dim3(1024), 0, st, partials, (int)nb, h + i0);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_gs_update(const double* V, long ld, int nv, const double* h, double* w, size_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_gs_update, dim3(blocks_for(n, 256)), dim3(256), 0, st, V, ld, nv, h, w, n);
   return hipGetLastError();
 }
 
@@ -256,3 +298,4 @@ hipError_t launch_zero_walls(double* vel, int nx, int ny, int nz, hipStream_t st
 }
 
 }  // namespace lk
+

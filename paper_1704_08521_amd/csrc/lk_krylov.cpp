@@ -1,7 +1,8 @@
 // Krylov-subspace drivers on SIMPLE-evaluated Krylov vectors (Section 3):
 // Newton steps whose corrections are solved by restarted GMRES with a
 // BiCGstab(2) hand-off on saturation, and the leading eigenvalues of eq. 7 by
-// implicitly restarted Arnoldi with modified Gram-Schmidt in float64.
+// implicitly restarted Arnoldi with classical Gram-Schmidt (repeated when the norm
+// drops) in float64.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -98,10 +99,11 @@ int vproject(lc_ctx* c, double* x, double* tmp) {
   return vcopy(c, tmp, x);
 }
 
-// Modified Gram-Schmidt of w against V[0..nv-1] with the coefficients kept in
-// device memory between the steps (one host synchronization per pass), and a
-// second pass when the norm drops below 1/sqrt(2) of its value before the pass.
-// h[0..nv-1] receive the coefficients, h[nv] the final norm of w.
+// Orthogonalizes w against the nv basis vectors of V: classical Gram-Schmidt (one
+// block dot-product pass and one update pass over the basis, coefficients staying on the
+// device), repeated once when the norm drops below 1/sqrt 2 of its value (the DGKS
+// criterion; twice-classical Gram-Schmidt is orthogonal to working precision).  h[0..nv)
+// receives the projections, h[nv] the final norm.
 int mgs(lc_ctx* c, const Basis& V, int nv, double* w, double* h) {
   if (nv + 1 > kSmall) return fail(c, LC_EINVAL, "basis too large");
   double before = 0.0;
@@ -111,14 +113,8 @@ int mgs(lc_ctx* c, const Basis& V, int nv, double* w, double* h) {
   std::fill(h, h + nv + 1, 0.0);
   double after = before;
   for (int pass = 0; pass < 2; ++pass) {
-    int np = 0;
-    KLAUNCH(c, LC_K_VECTOR, launch_dot_partials(V.at(0), w, c->nvel, c->partials, &np, c->stream));
-    KLAUNCH(c, LC_K_REDUCE, launch_sum(c->partials, np, c->dsmall, c->stream));
-    for (int i = 0; i < nv; ++i) {
-      const double* next = (i + 1 < nv) ? V.at(i + 1) : nullptr;
-      KLAUNCH(c, LC_K_VECTOR, launch_mgs(w, V.at(i), next, c->dsmall + i, 1.0, c->nvel, c->partials, &np, c->stream));
-      if (next) KLAUNCH(c, LC_K_REDUCE, launch_sum(c->partials, np, c->dsmall + i + 1, c->stream));
-    }
+    KLAUNCH(c, LC_K_VECTOR, launch_gs_dot(V.at(0), V.ld, nv, w, c->nvel, c->partials, c->dsmall, c->stream));
+    KLAUNCH(c, LC_K_VECTOR, launch_gs_update(V.at(0), V.ld, nv, c->dsmall, w, c->nvel, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->hsmall, c->dsmall, nv * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     double a2 = 0.0;
     rc = vdot(c, w, w, &a2);  // synchronizes the stream

@@ -630,13 +630,21 @@ int lc_project(lc_ctx* c, const double* w, double* v, double* p, int precision, 
     }
   }
   // SIMPLE loop (Section 3): v = w, p = 0; repeat {solve; v -= G phi; p += phi}
+  // The certificate of an FP64 pass (exact solve: it nearly always ends the loop) only
+  // reduces the norm; D v is then written again if another pass needs it.  FP32 passes
+  // (one more always follows at tight tolerances) keep D v from the certificate.
   for (int it = 0; it < max_iter; ++it) {
     rc = poisson(c, c->r, c->phi, pass_precision);
     if (rc) return rc;
     KLAUNCH(c, LC_K_CORRECT, launch_correct(c->g, w, c->phi, v, p, started || it > 0, c->stream));
     double nk = 0.0;
-    rc = vnorm_div(c, v, c->r, &nk);
+    const bool keep_r = pass_precision != LC_FP64;
+    rc = vnorm_div(c, v, keep_r ? c->r : nullptr, &nk);
     if (rc) return rc;
+    if (!keep_r && nk / n0 > tol && it + 1 < max_iter) {
+      rc = vnorm_div(c, v, c->r, &nk);
+      if (rc) return rc;
+    }
     S.iterations = it + 1;
     S.rho = nk / n0;
     if (it < 16) S.rho_hist[it] = S.rho;

@@ -247,7 +247,9 @@ typedef struct {
  * Outputs (host): re_cr, omega_cr (|Im Lambda| interpolated linearly in Re between the
  * last two evaluations); hist (NULL or 4 * max_evals doubles) rows (Re, Re Lambda,
  * |Im Lambda|, max |P R(U)| reached); n_evals.  Returns LC_ENOTCONV when max_evals
- * evaluations did not meet re_tol (outputs then hold the last secant iterate).
+ * evaluations did not meet re_tol; re_cr and omega_cr then come from the linear root
+ * between the evaluations closest to zero on either side (largest negative and
+ * smallest positive Re Lambda) when both exist, else from the last secant iterate.
  * Workspace: three velocity vectors (the stored steady states and a residual) plus
  * those of Newton and Arnoldi (library-owned). */
 int lc_critical_re(lc_ctx* ctx, double re0, double re1, const lc_critical_opts* opt, double* re_cr,

@@ -17,7 +17,10 @@ method on Re -> Re Lambda(Re); every evaluation is a Newton steady state at that
 (oracle.newton, sparse direct Jacobian solves), started from the linear extrapolation
 of the two previous steady states in Re, followed by ARPACK on the oracle's Krylov map
 (oracle.eigen.arpack).  The critical frequency is |Im Lambda| interpolated linearly
-in Re between the last two evaluations.
+in Re between the last two evaluations.  When the search does not meet its tolerance
+within max_evals (noise in Re Lambda from imperfect steady states), the reported values
+come instead from the linear root between the evaluations closest to zero on either side
+of it.
 """
 import numpy as np
 
@@ -83,7 +86,15 @@ def critical_re(g: Grid, re0, re1, U0, alpha=0.0, re_tol=1e-8, max_evals=12, new
             omega = wb + (wb - wa) * (rn - rb) / (rb - ra)
             return {"re_cr": rn, "omega_cr": omega, "converged": True, "history": hist}
         evaluate(rn, predict(flows, rn))
-    (ra, fa, wa), (rb, fb, wb) = hist[-2], hist[-1]
-    rn = secant_step(ra, fa, rb, fb) if fb != fa else rb
+    # not converged (noisy or slow): the linear root between the evaluations closest to
+    # zero on either side of it, when both exist; otherwise the last secant iterate
+    neg = [h for h in hist if h[1] < 0.0]
+    pos = [h for h in hist if h[1] > 0.0]
+    if neg and pos:
+        (ra, fa, wa), (rb, fb, wb) = max(neg, key=lambda h: h[1]), min(pos, key=lambda h: h[1])
+        rn = secant_step(ra, fa, rb, fb)
+    else:
+        (ra, fa, wa), (rb, fb, wb) = hist[-2], hist[-1]
+        rn = secant_step(ra, fa, rb, fb) if fb != fa else rb
     return {"re_cr": rn, "omega_cr": wb + (wb - wa) * (rn - rb) / (rb - ra), "converged": False,
             "history": hist}

@@ -662,7 +662,21 @@ extern "C" int lc_critical_re(lc_ctx* c, double re0, double re1, const lc_critic
     if ((int)R.size() >= o->max_evals) break;
     if ((rc = evaluate(rn))) return rc;
   }
-  const size_t b = R.size() - 1, a = b - 1;
+  size_t b = R.size() - 1, a = b - 1;
+  if (!converged) {
+    // noisy or slow: the linear root between the evaluations closest to zero on either
+    // side of it (largest negative and smallest positive Re Lambda), if they exist
+    int lo = -1, hi = -1;
+    for (size_t i = 0; i < R.size(); ++i) {
+      if (F[i] < 0.0 && (lo < 0 || F[i] > F[lo])) lo = (int)i;
+      if (F[i] > 0.0 && (hi < 0 || F[i] < F[hi])) hi = (int)i;
+    }
+    if (lo >= 0 && hi >= 0) {
+      a = lo;
+      b = hi;
+      rn = R[a] - F[a] * (R[b] - R[a]) / (F[b] - F[a]);
+    }
+  }
   *re_cr = rn;
   *omega_cr = W[b] + (W[b] - W[a]) * (rn - R[b]) / (R[b] - R[a]);
   return converged ? LC_OK : LC_ENOTCONV;

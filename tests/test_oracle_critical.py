@@ -95,3 +95,21 @@ def test_secant_search_finds_known_crossings(monkeypatch, kind):
     assert out["omega_cr"] == pytest.approx(omega, abs=1e-10)
     if kind == "linear":
         assert len(out["history"]) == 3  # two starts and one exact secant step
+
+
+def test_unconverged_search_reports_the_bracketing_root(monkeypatch):
+    """With noise of 1e-4 in Re Lambda the secant wanders near the root; the reported
+    value is then the linear root between the evaluations closest to zero on either side."""
+    monkeypatch.setattr(crit, "Newton", _StubNewton)
+    noise = iter([0.0, 0.0, 3e-4, -2e-4, 2.5e-4, -1e-4, 1.5e-4, 0.0])
+    lam = lambda re: complex((re - 1963.0) * 1e-4 + next(noise), 0.57)
+    out = crit.critical_re(None, 1940.0, 1990.0, np.zeros(3), re_tol=1e-9, max_evals=6,
+                           leading_fn=lambda g, U, re: lam(re))
+    assert not out["converged"]
+    hist = out["history"]
+    neg = max((h for h in hist if h[1] < 0), key=lambda h: h[1])
+    pos = min((h for h in hist if h[1] > 0), key=lambda h: h[1])
+    want = neg[0] - neg[1] * (pos[0] - neg[0]) / (pos[1] - neg[1])
+    assert out["re_cr"] == pytest.approx(want, rel=1e-14)
+    assert min(neg[0], pos[0]) <= out["re_cr"] <= max(neg[0], pos[0])
+    assert out["omega_cr"] == pytest.approx(0.57, abs=1e-12)

@@ -255,6 +255,30 @@ typedef struct {
 int lc_critical_re(lc_ctx* ctx, double re0, double re1, const lc_critical_opts* opt, double* re_cr,
                    double* omega_cr, double* hist, int* n_evals);
 
+/* ------------------------------------------ plane projections (Section 4) */
+
+/* Divergence-free projection of a velocity onto one family of coordinate planes
+ * (Section 4, eqs. 11-14) and its vector potential (eqs. 15-17).
+ *   which = 1: v1 = (u1, 0, w1), planes y = const;
+ *   which = 2: v2 = (0, v2, w2), planes x = const;
+ *   which = 3: v3 = (u3, v3, 0), planes z = const.
+ * out (velocity, packed u|v|w) receives the orthogonal projection, in the
+ * face-volume inner product, of the input's two kept components (its wall-normal
+ * faces taken as zero) onto the fields whose two-dimensional divergence vanishes
+ * in every such plane and whose wall-normal components vanish; the third
+ * component of out is zero.  The plane pressure solves D2 G2 phi = D2 b in each
+ * plane by the per-axis transforms of the pressure solver (two in-plane axes,
+ * FP64).  If psi is not NULL it receives the one non-zero component of the
+ * potential whose discrete curl is out, zero on the walls, on the cell edges
+ * normal to the planes, last index fastest:
+ *   which 1: Psi_y[k][j][i], (nz+1) x ny x (nx+1)  (x-face i, z-face k);
+ *   which 2: Psi_x[k][j][i], (nz+1) x (ny+1) x nx  (y-face j, z-face k);
+ *   which 3: Psi_z[k][j][i], nz x (ny+1) x (nx+1)  (x-face i, y-face j).
+ * v, out, psi: device, 8-byte aligned, caller-owned; out must not alias v.
+ * Uses the context's cell work arrays.  LC_EINVAL for a bad `which` or pointer,
+ * LC_ESTATE before a grid is set. */
+int lc_plane_project(lc_ctx* ctx, const double* v, int which, double* out, double* psi);
+
 /* ------------------------------------------------- learned correction guess */
 
 /* Not part of the paper's method: a small 3D convolutional network (3-level
@@ -340,7 +364,8 @@ int lc_dot(lc_ctx* ctx, const double* a, const double* b, double* out);
 #define LC_K_VECTOR 10    /* dot / axpy / scale / fill                       */
 #define LC_K_NN_FORWARD 11 /* network forward pass (all layers)              */
 #define LC_K_NN_MISC 12   /* network input/output conversions and fits       */
-#define LC_K_COUNT 13
+#define LC_K_PLANES 13    /* plane-projection right side, scaling, correction, potentials */
+#define LC_K_COUNT 14
 
 /* Enable (1) or disable (0) per-launch HIP-event timing on the context's
  * stream; enabling clears previous records.  Adds two event records per

@@ -138,6 +138,25 @@ class Context:
                                         self._ptr(v, self.nvel, "v"), self._ptr(p, self.ncell, "p")))
         return v, p
 
+    def psi_size(self, which):
+        """Entries of the vector potential of plane projection `which` (1, 2, 3)."""
+        nx, ny, nz = self.nx, self.ny, self.nz
+        return {1: (nz + 1) * ny * (nx + 1), 2: (nz + 1) * (ny + 1) * nx, 3: nz * (ny + 1) * (nx + 1)}[which]
+
+    def plane_project(self, v, which, out=None, psi=None, potential=True):
+        """Divergence-free projection of v onto the planes of family `which` (1: (u, w)
+        in y = const, 2: (v, w) in x = const, 3: (u, v) in z = const) and, if potential,
+        its vector potential (Section 4, eqs. 11-17).  Returns (out, psi or None)."""
+        if which not in (1, 2, 3):
+            raise ValueError("which must be 1, 2 or 3")
+        out = self.vel() if out is None else out
+        if potential and psi is None:
+            psi = _torch().zeros(self.psi_size(which), dtype=_torch().float64, device=self.device)
+        pp = self._ptr(psi, self.psi_size(which), "psi") if potential else None
+        self._check(self.lib.lc_plane_project(self._h, self._ptr(v, self.nvel, "v"), int(which),
+                                              self._ptr(out, self.nvel, "out"), pp))
+        return out, (psi if potential else None)
+
     # ------------------------------------------------------------ hot path
     def project(self, w, v=None, p=None, precision=FP64, tol=1e-8, max_iter=8):
         v = self.vel() if v is None else v

@@ -681,7 +681,7 @@ int lc_dot(lc_ctx* c, const double* a, const double* b, double* out) {
 
 static const char* kKernelNames[LC_K_COUNT] = {"momentum", "residual", "divergence", "correct",  "tp_x",
                                                 "tp_y",     "tp_z",     "eigscale",   "reduce",   "cast",
-                                                "vector",   "nn_forward", "nn_misc"};
+                                                "vector",   "nn_forward", "nn_misc",  "planes"};
 
 extern "C" const char* lc_profile_name(int k) { return (k >= 0 && k < LC_K_COUNT) ? kKernelNames[k] : nullptr; }
 

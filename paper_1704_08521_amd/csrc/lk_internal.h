@@ -157,6 +157,21 @@ hipError_t launch_uniform(double* x, size_t n, uint64_t seed, hipStream_t st);
 // Zero the wall-normal faces of a packed velocity.
 hipError_t launch_zero_walls(double* vel, int nx, int ny, int nz, hipStream_t st);
 
+// ---------------------------------------------------- plane projections
+// P = 1 keeps (u, w) (planes y = const), 2 keeps (v, w) (x = const), 3 keeps (u, v)
+// (z = const).
+// r = D2 b, b = the kept components of vel with the wall-normal faces zero.
+hipError_t launch_plane_rhs(const GridDev& g, int P, const double* vel, double* r, hipStream_t st);
+// t /= lx[i] + ly[j] + lz[k] (a null array adds nothing); zero where every index equals
+// its zero mode, a negative zero mode matching every index.
+hipError_t launch_plane_scale(double* t, int nx, int ny, int nz, const double* lx, const double* ly, const double* lz,
+                              int zx, int zy, int zz, hipStream_t st);
+// out = b - G2 phi on interior faces of the kept components, zero elsewhere.
+hipError_t launch_plane_correct(const GridDev& g, int P, const double* vel, const double* phi, double* out,
+                                hipStream_t st);
+// The potential of a projection by prefix sums from the walls.
+hipError_t launch_plane_potential(const GridDev& g, int P, const double* vel, double* psi, hipStream_t st);
+
 constexpr int kReduceBlock = 256;
 // Classical Gram-Schmidt: h[i] = V_i . w (i < nv; basis vectors ld apart; h on the device,
 // fixed-order sums), then w -= sum_i h[i] V_i.  partials holds kGsBlocks * kGsChunk doubles.

@@ -48,6 +48,9 @@ def parse():
                     help="instead of the Krylov-vector benchmark: critical Reynolds number of the N^3 cube "
                          "on the sine grid of eq. 5, lid along x (Newton continuation, then the secant "
                          "driver lc_critical_re); one JSON line")
+    ap.add_argument("--planes", action="store_true",
+                    help="instead of the Krylov-vector benchmark: only the plane projections and potentials "
+                         "(eqs. 11-17) at --size^3; one JSON line")
     return ap.parse_args()
 
 
@@ -219,6 +222,60 @@ PAPER_TABLE3_A0 = {100: (1963.74, 0.575370), 150: (1938.98, 0.581315), 200: (193
                    256: (1926.10, 0.584438)}
 
 
+# algorithmic HBM bytes per cell of the plane kernels of one projection with its potential:
+# right side (two components in, one cell value out: 24), mode-space scaling (16),
+# correction (two components and phi in, three components out: 48), prefix sums (16)
+PLANE_BYTES_PER_CELL = 24.0 + 16.0 + 48.0 + 16.0
+
+
+def time_planes(ctx, torch, v, steps=10):
+    """Plane projections v1, v2, v3 with their potentials (eqs. 11-17) of one input:
+    per family the mean wall time of a call (stream synchronized per call), then the
+    per-class HIP-event times of one profiled pass over the three families."""
+    n3 = ctx.nx * ctx.ny * ctx.nz
+    out = ctx.vel()
+    res = {}
+    for which in (1, 2, 3):
+        psi = torch.zeros(ctx.psi_size(which), dtype=torch.float64, device="cuda")
+        ctx.plane_project(v, which, out, psi)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.plane_project(v, which, out, psi)
+        torch.cuda.synchronize()
+        res[f"v{which}"] = {"ms_per_call": 1e3 * (time.perf_counter() - t0) / steps}
+    ctx.profile(True)
+    for _ in range(steps):
+        for which in (1, 2, 3):
+            psi = torch.zeros(ctx.psi_size(which), dtype=torch.float64, device="cuda")
+            ctx.plane_project(v, which, out, psi)
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    calls = 3 * steps
+    total = sum(ms for ms, _ in prof.values())
+    res["projections_per_s_gpu_time"] = calls / (total * 1e-3)
+    res["gpu_ms_per_projection"] = total / calls
+    res["classes_ms_per_projection"] = {k: ms / calls for k, (ms, _) in prof.items()}
+    if "planes" in prof:
+        ms = prof["planes"][0] / calls
+        gbs = PLANE_BYTES_PER_CELL * n3 / (ms * 1e-3) / 1e9
+        res["plane_kernels"] = {"ms_per_projection": ms, "algorithmic_bytes": PLANE_BYTES_PER_CELL * n3,
+                                "GB/s": gbs, "frac_hbm": gbs / PEAK_HBM_GBS}
+    return res
+
+
+def planes_run(n, lk, torch, steps):
+    import synth
+    ctx = lk.Context(n, n, n)
+    ctx.set_stretching("tanh", TANH_RATIO)
+    v = torch.from_numpy(synth.random_velocity(n, n, n, 1)).cuda()
+    log(f"[planes] {n}^3 tanh-{TANH_RATIO:g}: {steps} calls per family")
+    res = time_planes(ctx, torch, v, steps)
+    res = {"metric": "plane projections with potentials (eqs. 11-17) per second", "grid": [n, n, n],
+           "stretching": "tanh", "ratio": TANH_RATIO, **res}
+    print(json.dumps(res), flush=True)
+
+
 def critical_run(n, lk, torch):
     """Steady states continued from rest up to Re = 1930, then the secant search for the
     critical Reynolds number (the leading eigenvalue of eq. 7 crossing the imaginary
@@ -271,6 +328,10 @@ def main():
     if a.critical:
         torch.cuda.set_device(0)
         critical_run(a.critical, lk, torch)
+        return
+    if a.planes:
+        torch.cuda.set_device(0)
+        planes_run(a.size, lk, torch, a.steps)
         return
     n = a.size
     torch.cuda.set_device(0)
@@ -351,6 +412,8 @@ def main():
     log("[bench] Arnoldi cycle (m=30, k=6, one restart)")
     arnoldi = time_arnoldi(ctx, lk, torch)
     log(f"[bench] Arnoldi: {arnoldi['steps_per_s']:.1f} steps/s ({arnoldi['vectors']} vectors)")
+    planes = time_planes(ctx, torch, inputs[0])
+    log(f"[bench] plane projections: {planes['gpu_ms_per_projection']:.3f} ms GPU time each")
     out = {
         "metric": "Krylov vectors/s to 1e-8 rel. residual at 200^3 (plain/mixed/learned); % HBM peak",
         "value": forms["plain"]["value"],
@@ -370,6 +433,7 @@ def main():
                    "poisson": "tensor-product factorization"},
         "forms": forms,
         "arnoldi": arnoldi,
+        "planes": planes,
         "roofline": roof,
         "kernels": table,
     }

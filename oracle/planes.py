@@ -26,9 +26,15 @@ edges normal to the planes and vanish on the walls:
   Psi_z(i+1, j) = Psi_z(i, j) - dx_i v3(i, j).
 
 Each plane's Neumann problem is solved densely (minimum-norm least squares, which fixes
-the per-plane constant); meant for grids up to a few dozen cells per side.
+the per-plane constant); meant for grids up to a few dozen cells per side.  For sampling
+at large sizes, project_one_plane solves a single plane by itself: the same plane operator
+assembled explicitly as the sum of the two one-dimensional Neumann operators D_a G_a of its
+axes (a sparse matrix), one unknown fixed to zero (the plane gradient does not see the
+constant), a sparse direct solve.
 """
 import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
 
 from .fv import divergence, gradient, zero_walls
 from .grid import Grid
@@ -109,3 +115,63 @@ def curl_of_potential(g: Grid, psi, which):
         u[:] = np.diff(psi, axis=1) / Y.d[None, :, None]
         v[:] = -np.diff(psi, axis=2) / X.d[None, None, :]
     return g.pack(u, v, w)
+
+
+# ---------------------------------------------------------------- one plane, sparse
+def _neumann_1d(ax):
+    """D_a G_a along one axis on cell values: face gradients (phi_f - phi_(f-1)) / dd_f on
+    the interior faces, zero through the walls, then the cell differences over d_i."""
+    n = ax.n
+    f = np.arange(1, n)
+    G = sp.csr_matrix((np.concatenate([-1.0 / ax.dd[f], 1.0 / ax.dd[f]]),
+                       (np.concatenate([f, f]), np.concatenate([f - 1, f]))), shape=(n + 1, n))
+    i = np.arange(n)
+    D = sp.csr_matrix((np.concatenate([-1.0 / ax.d, 1.0 / ax.d]),
+                       (np.concatenate([i, i]), np.concatenate([i, i + 1]))), shape=(n, n + 1))
+    return (D @ G).tocsr()
+
+
+def project_one_plane(g: Grid, vec, which, index):
+    """One plane of projection `which`: the plane normal to the family's axis at cell
+    index `index`.  Returns (first, second, psi): the two kept components on that plane
+    as 2D arrays (slices of the packed components at the plane, in their natural index
+    order: which 1: u[:, index, :], w[:, index, :]; which 2: v[:, :, index], w[:, :, index];
+    which 3: u[index], v[index]) and the potential's slice at the plane."""
+    keep, axis = KEEP[which], NORMAL[which]
+    b = zero_walls(g, _mask(g, vec, keep))
+    bu, bv, bw = g.unpack(b)
+    rhs3 = divergence(g, b)
+    X, Y, Z = g.X, g.Y, g.Z
+    if which == 1:  # plane y = index: unknowns phi[k, i]
+        slow, fast, rhs = Z, X, rhs3[:, index, :]
+    elif which == 2:  # plane x = index: phi[k, j]
+        slow, fast, rhs = Z, Y, rhs3[:, :, index]
+    else:  # plane z = index: phi[j, i]
+        slow, fast, rhs = Y, X, rhs3[index]
+    A = (sp.kron(sp.identity(slow.n), _neumann_1d(fast)) + sp.kron(_neumann_1d(slow), sp.identity(fast.n))).tolil()
+    r = rhs.ravel().copy()
+    A[0, :] = 0.0
+    A[0, 0] = 1.0
+    r[0] = 0.0
+    phi = spla.spsolve(A.tocsc(), r).reshape(slow.n, fast.n)
+    # the two kept components minus the plane gradient, zero on the walls
+    gf = np.zeros((slow.n, fast.n + 1))
+    gf[:, 1:-1] = np.diff(phi, axis=1) / fast.dd[1:-1][None, :]
+    gs = np.zeros((slow.n + 1, fast.n))
+    gs[1:-1, :] = np.diff(phi, axis=0) / slow.dd[1:-1][:, None]
+    if which == 1:
+        first, second = bu[:, index, :] - gf, bw[:, index, :] - gs  # u (k, i), w (k, i)
+        psi = np.zeros((g.nz + 1, g.nx + 1))  # Psi_y[k, i]
+        for i in range(g.nx):
+            psi[:, i + 1] = psi[:, i] + X.d[i] * second[:, i]
+    elif which == 2:
+        first, second = bv[:, :, index] - gf, bw[:, :, index] - gs  # v (k, j), w (k, j)
+        psi = np.zeros((g.nz + 1, g.ny + 1))  # Psi_x[k, j]
+        for j in range(g.ny):
+            psi[:, j + 1] = psi[:, j] - Y.d[j] * second[:, j]
+    else:
+        first, second = bu[index] - gf, bv[index] - gs  # u (j, i), v (j, i)
+        psi = np.zeros((g.ny + 1, g.nx + 1))  # Psi_z[j, i]
+        for i in range(g.nx):
+            psi[:, i + 1] = psi[:, i] - X.d[i] * second[:, i]
+    return first, second, psi

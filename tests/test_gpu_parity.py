@@ -104,6 +104,30 @@ def test_divergence_and_correction(case):
 
 
 @pytest.mark.parametrize("case", CASES)
+def test_simple_pass_certificate_and_second_pass(case):
+    # one SIMPLE pass: its certificate equals the separate divergence norm of the stored
+    # v, and v, p are the plain correction; a second (FP32) pass solves with D v of the first
+    nx, ny, nz, kind = case
+    c, g, _ = ctx_for(nx, ny, nz, kind)
+    w_h = synth.random_velocity(nx, ny, nz, 9)
+    w = dev(w_h)
+    _, n0 = c.divergence(w)
+    for prec, rtol in ((1, 1e-9), (0, 1e-6)):
+        vo, po, st = c.project(w, precision=prec, tol=0.0, max_iter=1)
+        _, n1 = c.divergence(vo)
+        print(f"precision {prec}: rho {st['rho']:.6e} separate {n1 / n0:.6e}")
+        assert st["iterations"] == 1 and math.isclose(st["rho"], n1 / n0, rel_tol=rtol)
+        phi = host(po).reshape(nz, ny, nx)
+        assert rel(host(vo), fv.zero_walls(g, w_h) - fv.gradient(g, phi)) < 1e-12
+    vo, _, st = c.project(w, precision=1, tol=0.0, max_iter=2)
+    vo1, po1, _ = c.project(w, precision=1, tol=0.0, max_iter=1)
+    r1, _ = c.divergence(vo1)
+    phi2 = c.poisson_solve(r1, precision=1)
+    ref2 = host(vo1) - fv.zero_walls(g, fv.gradient(g, host(phi2).reshape(nz, ny, nx)))
+    assert st["iterations"] == 2 and rel(host(vo), ref2) < 1e-12
+
+
+@pytest.mark.parametrize("case", CASES)
 def test_poisson_solve(case):
     nx, ny, nz, kind = case
     c, g, _ = ctx_for(nx, ny, nz, kind)

@@ -4,7 +4,8 @@ Small grids: element-wise against the dense per-plane oracle (oracle.planes), ou
 psi to 1e-11 of their largest value (two transform pairs instead of three, so the bound
 of the 3D Poisson solve applies).  Grids on all three transform variants: matrix cores
 (mirror-symmetric axes up to 256 cells), folded half-size and full matrices (seeded
-random widths).  Larger grids, where the dense oracle is out of reach: the properties
+random widths).  Larger grids (200^3, 45 x 30 x 61), where the dense oracle is out of
+reach: whole sampled planes against the oracle's single-plane sparse solve, and the properties
 that fix an orthogonal projection onto the subspace at any size -- its output lies in
 the subspace (plane divergence, dropped component and walls), it keeps the subspace
 (curls of random potentials), it is self-adjoint in the face-volume inner product and
@@ -159,6 +160,33 @@ def test_plane_projection_properties_at_size(case, which):
         walls = [ps[:, 0], ps[:, -1], ps[:, :, 0], ps[:, :, -1]]
     for wall in walls:
         assert np.max(np.abs(wall)) < 1e-10 * np.abs(ps).max()
+
+
+@pytest.mark.parametrize("case", [((200, 200, 200), "tanh"), ((45, 30, 61), "sine")])
+def test_plane_projection_sampled_planes_at_size(case):
+    # whole planes against the oracle's single-plane sparse solve, at sizes the dense
+    # oracle cannot reach: the first, a middle and the last plane of each family
+    dims, kind = case
+    c, g = ctx_kind(*dims, kind)
+    b = synth.random_velocity(*dims, 93)
+    bd = dev(b)
+    for which in (1, 2, 3):
+        out, psi = c.plane_project(bd, which)
+        u, v, w = g.unpack(host(out))
+        shape = planes.potential(g, np.zeros(g.nvel()), which).shape
+        ps = host(psi).reshape(shape)
+        n = {1: g.ny, 2: g.nx, 3: g.nz}[which]
+        for idx in (0, n // 2 + 1, n - 1):
+            print(f"[plane] family {which} index {idx}", flush=True)
+            ref = planes.project_one_plane(g, b, which, idx)
+            if which == 1:
+                got = (u[:, idx, :], w[:, idx, :], ps[:, idx, :])
+            elif which == 2:
+                got = (v[:, :, idx], w[:, :, idx], ps[:, :, idx])
+            else:
+                got = (u[idx], v[idx], ps[idx])
+            for a, r in zip(got, ref):
+                assert rel(a, r) < 1e-10
 
 
 def test_plane_projection_rejects_bad_arguments():

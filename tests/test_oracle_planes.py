@@ -94,3 +94,27 @@ def test_potential_vanishes_on_walls_and_reproduces_the_projection(which):
         assert np.max(np.abs(wall)) < 1e-12 * scale
     back = planes.curl_of_potential(g, psi, which)
     assert np.allclose(back, p, rtol=0, atol=1e-11 * np.abs(p).max())
+
+
+@pytest.mark.parametrize("which", [1, 2, 3])
+@pytest.mark.parametrize("gi", [0, 1])
+def test_one_plane_sparse_solve_matches_the_dense_projection(which, gi):
+    # the single-plane sparse solve (for sampling large grids) against the dense
+    # projection and potential on every plane
+    g = grids()[gi]
+    b = np.random.default_rng(60 + 10 * gi + which).standard_normal(g.nvel())
+    p, _ = planes.project_plane(g, b, which)
+    u, v, w = g.unpack(p)
+    psi = planes.potential(g, p, which)
+    n = {1: g.ny, 2: g.nx, 3: g.nz}[which]
+    for idx in range(n):
+        first, second, ps = planes.project_one_plane(g, b, which, idx)
+        if which == 1:
+            ref = (u[:, idx, :], w[:, idx, :], psi[:, idx, :])
+        elif which == 2:
+            ref = (v[:, :, idx], w[:, :, idx], psi[:, :, idx])
+        else:
+            ref = (u[idx], v[idx], psi[idx])
+        for a, r in zip((first, second, ps), ref):
+            assert a.shape == r.shape
+            assert np.max(np.abs(a - r)) < 1e-12 * max(np.abs(r).max(), 1.0)

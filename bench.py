@@ -128,7 +128,8 @@ def transform_flops(n, lines, symmetric):
 
 
 def kernel_table(prof, n, symmetric=True):
-    """Per-kernel average durations and algorithmic rates."""
+    """Per-kernel average durations and algorithmic rates (algorithmic bytes or FLOPs per
+    launch over the launch's average HIP-event time)."""
     nx = ny = nz = n
     ncell = nx * ny * nz
     fu = 8.0 * ((nx + 1) * ny * nz + nx * (ny + 1) * nz + nx * ny * (nz + 1))  # bytes of a velocity

@@ -189,6 +189,20 @@ def test_plane_projection_sampled_planes_at_size(case):
                 assert rel(a, r) < 1e-10
 
 
+@pytest.mark.parametrize("which", [1, 2, 3])
+def test_plane_projection_of_zero_and_of_a_plane_gradient(which):
+    # degenerate inputs: zero gives exactly zero; a field whose kept components are a
+    # plane gradient (phi varying in all three directions) projects to zero
+    c, g = ctx_kind(17, 9, 12, "tanh")
+    out, psi = c.plane_project(dev(np.zeros(g.nvel())), which)
+    assert not np.any(host(out)) and not np.any(host(psi))
+    from oracle.fv import gradient
+    phi = synth.random_cells(17, 9, 12, 5)
+    gr = gradient(g, phi)
+    pg = host(c.plane_project(dev(gr), which, potential=False)[0])
+    assert np.max(np.abs(pg)) < 1e-11 * np.max(np.abs(gr))
+
+
 def test_plane_projection_rejects_bad_arguments():
     from paper_1704_08521_amd import LidKrylovError
     c, g = ctx_kind(6, 5, 4, "uniform")

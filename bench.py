@@ -48,6 +48,9 @@ def parse():
                     help="instead of the Krylov-vector benchmark: critical Reynolds number of the N^3 cube "
                          "on the sine grid of eq. 5, lid along x (Newton continuation, then the secant "
                          "driver lc_critical_re); one JSON line")
+    ap.add_argument("--poisson", choices=("tpf", "tpt"), default="tpf",
+                    help="pressure-solve route of the FP64 passes (transforms along x, y, z, or along y, z "
+                         "with tridiagonal solves along x)")
     ap.add_argument("--planes", action="store_true",
                     help="instead of the Krylov-vector benchmark: only the plane projections and potentials "
                          "(eqs. 11-17) at --size^3; one JSON line")
@@ -142,6 +145,7 @@ def kernel_table(prof, n, symmetric=True):
         "tp_y": ("alu", transform_flops(ny, nx * nz, symmetric)),
         "tp_z": ("alu", transform_flops(nz, nx * ny, symmetric)),
         "eigscale": ("hbm", 2 * fp),
+        "tridiag": ("hbm", 2 * fp),              # TPT: read the transformed field, write phi-hat
     }
     table = {}
     for name, (ms, launches) in prof.items():
@@ -340,6 +344,7 @@ def main():
     ctx.set_stretching("tanh", TANH_RATIO)
     ctx.set_re(RE)
     ctx.set_lid(0.0)
+    ctx.set_poisson_method(a.poisson)
     log(f"[bench] {n}^3 tanh-{TANH_RATIO:g} Re={RE:g}: building inputs")
     U = synthetic_base_flow(ctx, torch)
     ctx.set_base_flow(U)

@@ -129,6 +129,16 @@ int lc_residual(lc_ctx* ctx, const double* U, double* R);
  * receives (host) the volume-weighted norm sqrt(sum V r^2). */
 int lc_divergence(lc_ctx* ctx, const double* v, double* r, double* vnorm);
 
+/* Pressure-solve route of the FP64 passes (Section 3: the paper's TPF and TPT
+ * tensor-product solvers).  LC_POISSON_TPF (default): mode transforms along x, y and
+ * z and a division by the eigenvalue sums.  LC_POISSON_TPT: mode transforms along y and
+ * z and, along x, one tridiagonal solve per line (parallel cyclic reduction), for nx up
+ * to 1024 (larger nx uses TPF).  Both give the same solution up to rounding; FP32
+ * solves (the mixed form) always use TPF.  LC_EINVAL for an unknown method. */
+#define LC_POISSON_TPF 0
+#define LC_POISSON_TPT 1
+int lc_set_poisson_method(lc_ctx* ctx, int method);
+
 /* Pressure-correction Poisson solve (Section 3, step 1): (D G) phi = r with the
  * Neumann wall condition and sum V phi = 0.  r, phi: cell (may alias). */
 int lc_poisson_solve(lc_ctx* ctx, const double* r, double* phi, int precision);
@@ -365,7 +375,8 @@ int lc_dot(lc_ctx* ctx, const double* a, const double* b, double* out);
 #define LC_K_NN_FORWARD 11 /* network forward pass (all layers)              */
 #define LC_K_NN_MISC 12   /* network input/output conversions and fits       */
 #define LC_K_PLANES 13    /* plane-projection right side, scaling, correction, potentials */
-#define LC_K_COUNT 14
+#define LC_K_TRIDIAG 14   /* TPT tridiagonal solves along x                  */
+#define LC_K_COUNT 15
 
 /* Enable (1) or disable (0) per-launch HIP-event timing on the context's
  * stream; enabling clears previous records.  Adds two event records per

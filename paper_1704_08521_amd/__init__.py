@@ -97,6 +97,12 @@ class Context:
     def set_lid(self, alpha):
         self._check(self.lib.lc_set_lid(self._h, float(alpha)))
 
+    def set_poisson_method(self, method):
+        """Pressure-solve route of the FP64 passes: "tpf" (transforms along x, y, z) or
+        "tpt" (transforms along y, z; tridiagonal solves along x)."""
+        m = {"tpf": 0, "tpt": 1}[method]
+        self._check(self.lib.lc_set_poisson_method(self._h, m))
+
     def set_base_flow(self, U):
         self._check(self.lib.lc_set_base_flow(self._h, self._ptr(U, self.nvel, "U")))
 

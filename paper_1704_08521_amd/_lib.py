@@ -89,12 +89,13 @@ _SIGS = {
     "lc_net_train": (_I, [_P, _P, _I, _D, C.c_uint64, _P]),
     "lc_learned_guess": (_I, [_P, _P, _P, C.POINTER(_D)]),
     "lc_plane_project": (_I, [_P, _P, _I, _P, _P]),
+    "lc_set_poisson_method": (_I, [_P, _I]),
     "lc_profile_enable": (_I, [_P, _I]),
     "lc_profile_read": (_I, [_P, _I, C.POINTER(_D), C.POINTER(C.c_long)]),
     "lc_profile_name": (C.c_char_p, [_I]),
 }
 KERNEL_CLASSES = ["momentum", "residual", "divergence", "correct", "tp_x", "tp_y", "tp_z", "eigscale",
-                  "reduce", "cast", "vector", "nn_forward", "nn_misc", "planes"]
+                  "reduce", "cast", "vector", "nn_forward", "nn_misc", "planes", "tridiag"]
 
 _lib = None
 

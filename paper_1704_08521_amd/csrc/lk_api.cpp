@@ -289,6 +289,46 @@ int tp_solve(lc_ctx* c, const T* r, T* phi, T* t1, T* t2) {
   hipStream_t s = c->stream;
   const int n_yz = ny * nz, n_xz = nx * nz;
   const double* nul = nullptr;
+  if constexpr (sizeof(T) == sizeof(double)) {
+    if (c->poisson_method == LC_POISSON_TPT && nx <= tridiag_x_max()) {
+      // TPT: forward y and z, tridiagonal solves along x, backward z and y
+      if (Y.mf)
+        KLAUNCH(c, LC_K_TP_Y, launch_mff_left<T>(ny, n_xz, packs(Y, 0), packs(Y, 1), r, t1, nx, pl, nx, s));
+      else if (Y.sym)
+        KLAUNCH(c, LC_K_TP_Y, launch_tpf_left<T>(ny, n_xz, half(Y, 0), half(Y, 1), r, t1, nx, pl, nx, nul, nul, nul, 1,
+                                                 0, 0, 0, s));
+      else
+        KLAUNCH(c, LC_K_TP_Y, launch_tp_left<T>(ny, n_xz, ny, pick(Y, 0), r, t1, nx, pl, nx, nul, nul, nul, 1, 0, 0, 0,
+                                                s));
+      if (Z.mf)
+        KLAUNCH(c, LC_K_TP_Z, launch_mff_left<T>(nz, (int)pl, packs(Z, 0), packs(Z, 1), t1, t2, (int)pl, 0, pl, s));
+      else if (Z.sym)
+        KLAUNCH(c, LC_K_TP_Z, launch_tpf_left<T>(nz, (int)pl, half(Z, 0), half(Z, 1), t1, t2, (int)pl, 0, pl, nul, nul,
+                                                 nul, 1, 0, 0, 0, s));
+      else
+        KLAUNCH(c, LC_K_TP_Z, launch_tp_left<T>(nz, (int)pl, nz, pick(Z, 0), t1, t2, (int)pl, 0, pl, nul, nul, nul, 1, 0,
+                                                0, 0, s));
+      KLAUNCH(c, LC_K_TRIDIAG,
+              launch_tridiag_x(c->g, lams(Y), lams(Z), c->zero_mode[1], c->zero_mode[2], t2, t1, s));
+      if (Z.mf)
+        KLAUNCH(c, LC_K_TP_Z, launch_mfu_left<T>(nz, (int)pl, packs(Z, 2), packs(Z, 3), t1, t2, (int)pl, 0, pl, nul,
+                                                 nul, nul, 1, 0, 0, 0, s));
+      else if (Z.sym)
+        KLAUNCH(c, LC_K_TP_Z, launch_tpu_left<T>(nz, (int)pl, half(Z, 2), half(Z, 3), t1, t2, (int)pl, 0, pl, s));
+      else
+        KLAUNCH(c, LC_K_TP_Z, launch_tp_left<T>(nz, (int)pl, nz, pick(Z, 1), t1, t2, (int)pl, 0, pl, nul, nul, nul, 1, 0,
+                                                0, 0, s));
+      if (Y.mf)
+        KLAUNCH(c, LC_K_TP_Y, launch_mfu_left<T>(ny, n_xz, packs(Y, 2), packs(Y, 3), t2, phi, nx, pl, nx, nul, nul, nul,
+                                                 1, 0, 0, 0, s));
+      else if (Y.sym)
+        KLAUNCH(c, LC_K_TP_Y, launch_tpu_left<T>(ny, n_xz, half(Y, 2), half(Y, 3), t2, phi, nx, pl, nx, s));
+      else
+        KLAUNCH(c, LC_K_TP_Y, launch_tp_left<T>(ny, n_xz, ny, pick(Y, 1), t2, phi, nx, pl, nx, nul, nul, nul, 1, 0, 0, 0,
+                                                s));
+      return LC_OK;
+    }
+  }
   // forward: x (contiguous lines), y (columns (k, i), rows nx apart), z (rows nx*ny apart),
   // the division by lam_x + lam_y + lam_z fused into the z transform; a mirror-symmetric
   // axis uses the folded half-size transforms (modes parity-sorted)
@@ -499,6 +539,13 @@ int lc_get_grid(const lc_ctx* c, double* xf, double* yf, double* zf) {
   return LC_OK;
 }
 
+int lc_set_poisson_method(lc_ctx* c, int method) {
+  if (!c) return LC_EINVAL;
+  if (method != LC_POISSON_TPF && method != LC_POISSON_TPT) return fail(c, LC_EINVAL, "unknown Poisson method %d", method);
+  c->poisson_method = method;
+  return LC_OK;
+}
+
 int lc_set_re(lc_ctx* c, double re) {
   if (!c) return LC_EINVAL;
   if (!(re > 0.0) || !std::isfinite(re)) return fail(c, LC_EINVAL, "Re must be positive and finite");
@@ -681,7 +728,7 @@ int lc_dot(lc_ctx* c, const double* a, const double* b, double* out) {
 
 static const char* kKernelNames[LC_K_COUNT] = {"momentum", "residual", "divergence", "correct",  "tp_x",
                                                 "tp_y",     "tp_z",     "eigscale",   "reduce",   "cast",
-                                                "vector",   "nn_forward", "nn_misc",  "planes"};
+                                                "vector",   "nn_forward", "nn_misc",  "planes",  "tridiag"};
 
 extern "C" const char* lc_profile_name(int k) { return (k >= 0 && k < LC_K_COUNT) ? kKernelNames[k] : nullptr; }
 

@@ -157,6 +157,14 @@ hipError_t launch_uniform(double* x, size_t n, uint64_t seed, hipStream_t st);
 // Zero the wall-normal faces of a packed velocity.
 hipError_t launch_zero_walls(double* vel, int nx, int ny, int nz, hipStream_t st);
 
+// ---------------------------------------------------- TPT tridiagonal x step
+// For every x-line (k, j) of a (y, z)-transformed cell field: (D_x G_x + ly[j] + lz[k]) out
+// = in; the line (zk, zj) is the singular one (solution with zero d-weighted mean).
+// Lines of up to tridiag_x_max() cells.
+int tridiag_x_max();
+hipError_t launch_tridiag_x(const GridDev& g, const double* ly, const double* lz, int zj, int zk, const double* in,
+                            double* out, hipStream_t st);
+
 // ---------------------------------------------------- plane projections
 // P = 1 keeps (u, w) (planes y = const), 2 keeps (v, w) (x = const), 3 keeps (u, v)
 // (z = const).

@@ -251,3 +251,65 @@ def test_krylov_vector_asymmetric_grids(case):
     vo, po, st = c.krylov_vector(dev(v), tol=1e-10)
     ref_v, _ = simple.Projector(g).krylov_vector(U, v, 650.0)
     assert st["converged"] and rel(host(vo), ref_v) < 1e-10
+
+
+# The TPT route of the pressure solve (transforms along y and z, tridiagonal solves along x)
+# against the same oracle solves, on the symmetric, odd and asymmetric grids and at 200^3.
+@pytest.mark.parametrize("case", CASES)
+def test_poisson_solve_tpt(case):
+    nx, ny, nz, kind = case
+    c, g, U = ctx_for(nx, ny, nz, kind)
+    c.set_poisson_method("tpt")
+    r = synth.random_cells(nx, ny, nz, 5)
+    V = g.volumes()
+    r = r - np.sum(V * r) / np.sum(V)
+    ref = poisson.PoissonFD(g).solve(r)
+    phi = host(c.poisson_solve(dev(r.ravel()))).reshape(nz, ny, nx)
+    assert rel(phi, ref) < 1e-11
+    v = synth.random_velocity(nx, ny, nz, 6)
+    vo, po, st = c.krylov_vector(dev(v), tol=1e-10)
+    ref_v, ref_p = simple.Projector(g).krylov_vector(U, v, 700.0)
+    assert st["converged"] and st["iterations"] <= 2
+    assert rel(host(vo), ref_v) < 1e-10 and rel(host(po).reshape(nz, ny, nx), ref_p) < 1e-10
+
+
+@pytest.mark.parametrize("case", ASYM)
+def test_poisson_solve_tpt_asymmetric_grids(case):
+    dims, sym = case
+    c, g, _ = ctx_faces(dims, sym)
+    c.set_poisson_method("tpt")
+    nx, ny, nz = dims
+    r = synth.random_cells(nx, ny, nz, 7)
+    V = g.volumes()
+    r = r - np.sum(V * r) / np.sum(V)
+    ref = poisson.PoissonFD(g).solve(r)
+    phi = host(c.poisson_solve(dev(r.ravel()))).reshape(nz, ny, nx)
+    assert rel(phi, ref) < 1e-11
+
+
+def test_tpt_full_size_200():
+    # the benchmark's workload: TPT against TPF on the same right side and the TPT Krylov
+    # vector against the oracle, full fields
+    nx = 200
+    c, g, U = ctx_for(nx, nx, nx, "tanh", re=1900.0, alpha=0.0, seed=11)
+    r = synth.random_cells(nx, nx, nx, 13)
+    V = g.volumes()
+    r = r - np.sum(V * r) / np.sum(V)
+    rd = dev(r.ravel())
+    phi_f = host(c.poisson_solve(rd))
+    c.set_poisson_method("tpt")
+    phi_t = host(c.poisson_solve(rd))
+    print(f"TPT vs TPF at 200^3: {rel(phi_t, phi_f):.3e}")
+    assert rel(phi_t, phi_f) < 1e-11
+    v = synth.random_velocity(nx, nx, nx, 12)
+    vo, _, st = c.krylov_vector(dev(v), tol=1e-8)
+    assert st["converged"] and st["rho"] <= 1e-8
+    ref_v, _ = simple.Projector(g).krylov_vector(U, v, 1900.0)
+    assert rel(host(vo), ref_v) < 1e-10
+
+
+def test_poisson_method_rejects_unknown():
+    from paper_1704_08521_amd import LidKrylovError
+    c, g, _ = ctx_for(8, 8, 8, "uniform")
+    with pytest.raises(LidKrylovError):
+        c._check(c.lib.lc_set_poisson_method(c._h, 7))

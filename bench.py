@@ -48,9 +48,9 @@ def parse():
                     help="instead of the Krylov-vector benchmark: critical Reynolds number of the N^3 cube "
                          "on the sine grid of eq. 5, lid along x (Newton continuation, then the secant "
                          "driver lc_critical_re); one JSON line")
-    ap.add_argument("--poisson", choices=("tpf", "tpt"), default="tpf",
-                    help="pressure-solve route of the FP64 passes (transforms along x, y, z, or along y, z "
-                         "with tridiagonal solves along x)")
+    ap.add_argument("--poisson", choices=("tpt", "tpf"), default="tpt",
+                    help="pressure-solve route of the FP64 passes (transforms along y, z with tridiagonal "
+                         "solves along x, or transforms along x, y, z)")
     ap.add_argument("--planes", action="store_true",
                     help="instead of the Krylov-vector benchmark: only the plane projections and potentials "
                          "(eqs. 11-17) at --size^3; one JSON line")

@@ -69,7 +69,7 @@ struct lc_ctx {
   AxisModes modes[3];
   void* modes_mem = nullptr;
   int zero_mode[3] = {0, 0, 0};
-  int poisson_method = 0;  // LC_POISSON_TPF or LC_POISSON_TPT
+  int poisson_method = 1;  // LC_POISSON_TPT (default) or LC_POISSON_TPF
   // fields
   double* U = nullptr;   // base flow (velocity)
   double* w = nullptr;   // momentum work vector (velocity)

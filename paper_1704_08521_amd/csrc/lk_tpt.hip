@@ -2,10 +2,15 @@
 // Poisson solve by the TPT route of Section 3 (mode transforms in two directions, a
 // tridiagonal solve in the third).  For every x-line (k, j) of the transformed field,
 // (L_x + ly[j] + lz[k]) phi = rhs, with L_x = D_x G_x on the cells of the line (zero flux
-// through the walls), by parallel cyclic reduction in LDS, one block per line.  The line
-// whose shift is zero (the zero modes of y and z) is singular: its first equation is
-// replaced by phi_0 = 0 and the solution is re-centred to zero d-weighted mean, which
-// sets the constant mode to zero as the transform route does.
+// through the walls).  One wave per line, by the partition method: lane p owns the M
+// consecutive rows of segment p and eliminates its interior rows in registers (one
+// Thomas sweep with three right sides), which leaves one unknown per segment, its last
+// row; those form a tridiagonal system (the Schur complement, diagonally dominant like
+// the line's own matrix) solved by cyclic reduction across the lanes with shuffles; each
+// lane then recovers its interior rows.  The line whose shift is zero (the zero modes of
+// y and z) is singular: its first equation is replaced by phi_0 = 0 and the solution is
+// re-centred to zero d-weighted mean, which sets the constant mode to zero as the
+// transform route does.
 #include <hip/hip_runtime.h>
 
 #include "lk_device.h"
@@ -14,18 +19,7 @@
 namespace lk {
 namespace {
 
-template <int B>
-__device__ __forceinline__ double block_total(double x, double* red) {
-  // every thread gets the block sum (B threads, B / 64 waves)
-  x = wave_sum(x);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  if (lane == 0) red[wid] = x;
-  __syncthreads();
-  double t = 0.0;
-  for (int q = 0; q < B / 64; ++q) t += red[q];
-  __syncthreads();
-  return t;
-}
+constexpr int kTriLinesPerBlock = 4;  // one wave per line
 
 // 1 / a to FP64 accuracy: the hardware reciprocal refined by two Newton steps
 __device__ __forceinline__ double rcp64(double a) {
@@ -36,96 +30,181 @@ __device__ __forceinline__ double rcp64(double a) {
   return fma(e, y, y);
 }
 
-template <int B>
-__global__ void __launch_bounds__(B) k_tridiag_x(const double* __restrict__ rd, const double* __restrict__ rdd,
-                                                 const double* __restrict__ dx, int n, int ny,
-                                                 const double* __restrict__ ly, const double* __restrict__ lz,
-                                                 int zj, int zk, const double* __restrict__ in,
-                                                 double* __restrict__ out) {
-  __shared__ double sa[B], srb[B], sc[B], sd[B];  // srb: reciprocals of the diagonal
-  __shared__ double red[B / 64];
-  const long line = blockIdx.x;  // k * ny + j
+template <int M>
+__global__ void __launch_bounds__(64 * kTriLinesPerBlock) k_tridiag_x(
+    const double* __restrict__ rd, const double* __restrict__ rdd, const double* __restrict__ dx, int n, int ny,
+    long lines, const double* __restrict__ ly, const double* __restrict__ lz, int zj, int zk,
+    const double* __restrict__ in, double* __restrict__ out) {
+  const int lane = (int)(threadIdx.x & 63);
+  const long line = (long)blockIdx.x * kTriLinesPerBlock + (long)(threadIdx.x >> 6);
+  if (line >= lines) return;  // uniform per wave
   const int j = (int)(line % ny), k = (int)(line / ny);
-  const int i = threadIdx.x;
   const double shift = ly[j] + lz[k];
   const bool sing = (j == zj) && (k == zk);
-  // rows i >= n are the identity with a zero right side, coupled to nothing
-  double a = 0.0, b = 1.0, c = 0.0, d = 0.0;
-  if (i < n) {
-    const double lo = (i > 0) ? rdd[i] * rd[i] : 0.0;
-    const double up = (i + 1 < n) ? rdd[i + 1] * rd[i] : 0.0;
-    a = lo;
-    c = up;
-    b = shift - (lo + up);
-    d = in[(size_t)line * n + i];
-    if (sing && i == 0) {
-      a = 0.0;
-      b = 1.0;
-      c = 0.0;
-      d = 0.0;
+  const int P = (n + M - 1) / M;  // segments (lanes in use)
+  const int s0 = lane * M;
+  const int L = (lane < P) ? min(M, n - s0) : 0;  // rows of this lane's segment
+  const double* src = in + (size_t)line * n;
+  // the segment's rows: a x_{r-1} + b x_r + c x_{r+1} = d (identity rows beyond L)
+  double ra[M], rb[M], rc[M], rv[M];
+#pragma unroll
+  for (int t = 0; t < M; ++t) {
+    const int r = s0 + t;
+    double a = 0.0, b = 1.0, c = 0.0, d = 0.0;
+    if (t < L) {
+      a = (r > 0) ? rdd[r] * rd[r] : 0.0;
+      c = (r + 1 < n) ? rdd[r + 1] * rd[r] : 0.0;
+      b = shift - (a + c);
+      d = src[r];
+      if (sing && r == 0) {
+        a = 0.0;
+        b = 1.0;
+        c = 0.0;
+        d = 0.0;
+      }
+    }
+    ra[t] = a;
+    rb[t] = b;
+    rc[t] = c;
+    rv[t] = d;
+  }
+  // interior rows 0 .. q-1 in terms of the two segment ends z_{p-1} (previous lane's last
+  // row) and z_p (own last row): x = Y - V z_{p-1} - W z_p
+  const int q = L - 1;
+  double Y[M], V[M], W[M], cp[M];
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    Y[i] = 0.0;
+    V[i] = 0.0;
+    W[i] = 0.0;
+    cp[i] = 0.0;
+  }
+#pragma unroll
+  for (int i = 0; i < M - 1; ++i) {
+    if (i < q) {
+      const double sub = (i > 0) ? ra[i] : 0.0;
+      const double den = rb[i] - ((i > 0) ? sub * cp[i - 1] : 0.0);
+      const double r = rcp64(den);
+      cp[i] = ((i < q - 1) ? rc[i] : 0.0) * r;
+      Y[i] = (rv[i] - ((i > 0) ? sub * Y[i - 1] : 0.0)) * r;
+      V[i] = (((i == 0) ? ra[0] : 0.0) - ((i > 0) ? sub * V[i - 1] : 0.0)) * r;
+      W[i] = (((i == q - 1) ? rc[i] : 0.0) - ((i > 0) ? sub * W[i - 1] : 0.0)) * r;
     }
   }
-  // after the steps with strides 1, 2, 4, ... < n every row couples only to rows at least
-  // n away: all rows are decoupled.  A row's diagonal enters its neighbours only through
-  // its reciprocal.
-  for (int s = 1; s < n; s <<= 1) {
-    sa[i] = a;
-    srb[i] = rcp64(b);
-    sc[i] = c;
-    sd[i] = d;
-    __syncthreads();
-    const int im = i - s, ip = i + s;
-    double an = 0.0, cn = 0.0, bn = b, dn = d;
-    if (im >= 0) {
-      const double k1 = a * srb[im];
-      an = -sa[im] * k1;
-      bn -= sc[im] * k1;
-      dn -= sd[im] * k1;
+#pragma unroll
+  for (int i = M - 3; i >= 0; --i) {
+    if (i < q - 1) {
+      Y[i] -= cp[i] * Y[i + 1];
+      V[i] -= cp[i] * V[i + 1];
+      W[i] -= cp[i] * W[i + 1];
     }
-    if (ip < B) {
-      const double k2 = c * srb[ip];
-      cn = -sc[ip] * k2;
-      bn -= sa[ip] * k2;
-      dn -= sd[ip] * k2;
+  }
+  // the segment's first row and the row before its last, as (Y, V, W) of the ends; with no
+  // interior rows the first row is z_p itself and the row before the last is z_{p-1}
+  double Yf = 0.0, Vf = 0.0, Wf = 0.0, Yl = 0.0, Vl = 0.0, Wl = 0.0;
+  double ae = 0.0, be = 1.0, ce = 0.0, de = 0.0;
+  if (q >= 1) {
+    Yf = Y[0];
+    Vf = V[0];
+    Wf = W[0];
+  } else if (q == 0) {
+    Wf = -1.0;
+    Vl = -1.0;
+  }
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    if (i == q - 1) {
+      Yl = Y[i];
+      Vl = V[i];
+      Wl = W[i];
     }
-    __syncthreads();
-    a = an;
-    b = bn;
-    c = cn;
-    d = dn;
+    if (i == L - 1) {
+      ae = ra[i];
+      be = rb[i];
+      ce = rc[i];
+      de = rv[i];
+    }
   }
-  double x = d / b;
-  if (sing) {  // block-uniform branch
-    const double w = (i < n) ? dx[i] : 0.0;
-    const double mean = block_total<B>(w * x, red) / block_total<B>(w, red);
-    x -= mean;
+  // the last row's equation in the segment ends: al z_{p-1} + bt z_p + ga z_{p+1} = dl
+  const double Yn = __shfl_down(Yf, 1), Vn = __shfl_down(Vf, 1), Wn = __shfl_down(Wf, 1);
+  double al = 0.0, bt = 1.0, ga = 0.0, dl = 0.0;
+  if (L > 0) {
+    al = -ae * Vl;
+    bt = be - ae * Wl - ce * Vn;
+    ga = -ce * Wn;
+    dl = de - ae * Yl - ce * Yn;
   }
-  if (i < n) out[(size_t)line * n + i] = x;
+  // cyclic reduction across the lanes (identity rows beyond P couple to nothing)
+  for (int st = 1; st < P; st <<= 1) {
+    const double rbt = rcp64(bt);
+    const double am = __shfl_up(al, st), gm = __shfl_up(ga, st), dm = __shfl_up(dl, st), rm = __shfl_up(rbt, st);
+    const double ap = __shfl_down(al, st), gp = __shfl_down(ga, st), dp = __shfl_down(dl, st),
+                 rp = __shfl_down(rbt, st);
+    double an = 0.0, gn = 0.0, bn = bt, dn = dl;
+    if (lane >= st) {
+      const double k1 = al * rm;
+      an = -am * k1;
+      bn -= gm * k1;
+      dn -= dm * k1;
+    }
+    if (lane + st < 64) {
+      const double k2 = ga * rp;
+      gn = -gp * k2;
+      bn -= ap * k2;
+      dn -= dp * k2;
+    }
+    al = an;
+    bt = bn;
+    ga = gn;
+    dl = dn;
+  }
+  const double z = dl / bt;
+  const double zu = __shfl_up(z, 1);  // every lane takes part in the shuffle
+  const double zl = (lane > 0) ? zu : 0.0;
+  double x[M];
+#pragma unroll
+  for (int i = 0; i < M; ++i) x[i] = (i < q) ? Y[i] - V[i] * zl - W[i] * z : (i == q ? z : 0.0);
+  if (sing) {  // uniform per wave
+    double sw = 0.0, swx = 0.0;
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      if (i < L) {
+        const double w = dx[s0 + i];
+        sw += w;
+        swx += w * x[i];
+      }
+    }
+    // (the wave sums are complete in lane 0: broadcast them)
+    const double mean = __shfl(wave_sum(swx), 0) / __shfl(wave_sum(sw), 0);
+#pragma unroll
+    for (int i = 0; i < M; ++i) x[i] -= mean;
+  }
+  double* dst = out + (size_t)line * n;
+#pragma unroll
+  for (int i = 0; i < M; ++i)
+    if (i < L) dst[s0 + i] = x[i];
 }
 
 }  // namespace
 
-int tridiag_x_max() { return 1024; }
+int tridiag_x_max() { return 64 * 16; }
 
 hipError_t launch_tridiag_x(const GridDev& g, const double* ly, const double* lz, int zj, int zk, const double* in,
                             double* out, hipStream_t st) {
   const int n = g.x.n, ny = g.y.n, nz = g.z.n;
-  const unsigned lines = (unsigned)((long)ny * nz);
+  const long lines = (long)ny * nz;
+  const dim3 grid((unsigned)((lines + kTriLinesPerBlock - 1) / kTriLinesPerBlock)), block(64 * kTriLinesPerBlock);
+  const double *rd = g.x.rd, *rdd = g.x.rdd, *dx = g.x.d;
   if (n <= 64)
-    hipLaunchKernelGGL(k_tridiag_x<64>, dim3(lines), dim3(64), 0, st, g.x.rd, g.x.rdd, g.x.d, n, ny, ly, lz, zj, zk, in,
-                       out);
+    hipLaunchKernelGGL(k_tridiag_x<1>, grid, block, 0, st, rd, rdd, dx, n, ny, lines, ly, lz, zj, zk, in, out);
   else if (n <= 128)
-    hipLaunchKernelGGL(k_tridiag_x<128>, dim3(lines), dim3(128), 0, st, g.x.rd, g.x.rdd, g.x.d, n, ny, ly, lz, zj, zk,
-                       in, out);
+    hipLaunchKernelGGL(k_tridiag_x<2>, grid, block, 0, st, rd, rdd, dx, n, ny, lines, ly, lz, zj, zk, in, out);
   else if (n <= 256)
-    hipLaunchKernelGGL(k_tridiag_x<256>, dim3(lines), dim3(256), 0, st, g.x.rd, g.x.rdd, g.x.d, n, ny, ly, lz, zj, zk,
-                       in, out);
+    hipLaunchKernelGGL(k_tridiag_x<4>, grid, block, 0, st, rd, rdd, dx, n, ny, lines, ly, lz, zj, zk, in, out);
   else if (n <= 512)
-    hipLaunchKernelGGL(k_tridiag_x<512>, dim3(lines), dim3(512), 0, st, g.x.rd, g.x.rdd, g.x.d, n, ny, ly, lz, zj, zk,
-                       in, out);
+    hipLaunchKernelGGL(k_tridiag_x<8>, grid, block, 0, st, rd, rdd, dx, n, ny, lines, ly, lz, zj, zk, in, out);
   else if (n <= 1024)
-    hipLaunchKernelGGL(k_tridiag_x<1024>, dim3(lines), dim3(1024), 0, st, g.x.rd, g.x.rdd, g.x.d, n, ny, ly, lz, zj, zk,
-                       in, out);
+    hipLaunchKernelGGL(k_tridiag_x<16>, grid, block, 0, st, rd, rdd, dx, n, ny, lines, ly, lz, zj, zk, in, out);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

@@ -253,13 +253,15 @@ def test_krylov_vector_asymmetric_grids(case):
     assert st["converged"] and rel(host(vo), ref_v) < 1e-10
 
 
-# The TPT route of the pressure solve (transforms along y and z, tridiagonal solves along x)
-# against the same oracle solves, on the symmetric, odd and asymmetric grids and at 200^3.
+# Both routes of the pressure solve, each selected explicitly (TPT, the default: transforms
+# along y and z, tridiagonal solves along x; TPF: transforms along x, y and z) against the
+# same oracle solves, on the symmetric, odd and asymmetric grids and at 200^3.
+@pytest.mark.parametrize("method", ["tpt", "tpf"])
 @pytest.mark.parametrize("case", CASES)
-def test_poisson_solve_tpt(case):
+def test_poisson_solve_each_route(case, method):
     nx, ny, nz, kind = case
     c, g, U = ctx_for(nx, ny, nz, kind)
-    c.set_poisson_method("tpt")
+    c.set_poisson_method(method)
     r = synth.random_cells(nx, ny, nz, 5)
     V = g.volumes()
     r = r - np.sum(V * r) / np.sum(V)
@@ -273,11 +275,12 @@ def test_poisson_solve_tpt(case):
     assert rel(host(vo), ref_v) < 1e-10 and rel(host(po).reshape(nz, ny, nx), ref_p) < 1e-10
 
 
+@pytest.mark.parametrize("method", ["tpt", "tpf"])
 @pytest.mark.parametrize("case", ASYM)
-def test_poisson_solve_tpt_asymmetric_grids(case):
+def test_poisson_solve_each_route_asymmetric_grids(case, method):
     dims, sym = case
     c, g, _ = ctx_faces(dims, sym)
-    c.set_poisson_method("tpt")
+    c.set_poisson_method(method)
     nx, ny, nz = dims
     r = synth.random_cells(nx, ny, nz, 7)
     V = g.volumes()
@@ -287,15 +290,31 @@ def test_poisson_solve_tpt_asymmetric_grids(case):
     assert rel(phi, ref) < 1e-11
 
 
-def test_tpt_full_size_200():
-    # the benchmark's workload: TPT against TPF on the same right side and the TPT Krylov
-    # vector against the oracle, full fields
+@pytest.mark.parametrize("n", [1000, 300])
+def test_tpt_long_lines(n):
+    # x-lines beyond 256 cells (8 and 16 rows per lane) against TPF on a thin grid
+    c, g, _ = ctx_for(n, 3, 4, "tanh")
+    r = synth.random_cells(n, 3, 4, 17)
+    V = g.volumes()
+    r = r - np.sum(V * r) / np.sum(V)
+    rd = dev(r.ravel())
+    c.set_poisson_method("tpf")
+    phi_f = host(c.poisson_solve(rd))
+    c.set_poisson_method("tpt")
+    phi_t = host(c.poisson_solve(rd))
+    assert rel(phi_t, phi_f) < 1e-10
+
+
+def test_routes_agree_full_size_200():
+    # the benchmark's workload: TPT against TPF on the same right side, and the TPT
+    # Krylov vector against the oracle, full fields
     nx = 200
     c, g, U = ctx_for(nx, nx, nx, "tanh", re=1900.0, alpha=0.0, seed=11)
     r = synth.random_cells(nx, nx, nx, 13)
     V = g.volumes()
     r = r - np.sum(V * r) / np.sum(V)
     rd = dev(r.ravel())
+    c.set_poisson_method("tpf")
     phi_f = host(c.poisson_solve(rd))
     c.set_poisson_method("tpt")
     phi_t = host(c.poisson_solve(rd))

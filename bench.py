@@ -1,8 +1,8 @@
 """Krylov vectors per second at 200^3 on one MI355X.
 
 One step = one Krylov vector (eqs. 8-10): the linearized momentum stencil, the
-SIMPLE projection (divergence, tensor-product pressure-correction solve,
-velocity/pressure correction, divergence certificate) to a relative divergence
+SIMPLE projection (divergence, tensor-product pressure-correction solve (TPT for
+FP64 unless --poisson tpf), velocity/pressure correction, divergence certificate) to a relative divergence
 residual rho <= 1e-8, on a 200^3 tanh-stretched grid (centre/wall spacing 10),
 Re = 1900, lid along x.  Inputs are seeded (SplitMix64) and resident in HBM
 before the timed region.  Three forms: plain FP64, mixed (FP32 solves inside
@@ -11,7 +11,8 @@ trained beforehand on a 64^3 grid with pairs the method generates, then mixed
 passes).
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--size 200] [--no-cpu]
-                    [--train-steps 300]
+                    [--train-steps 300] [--poisson tpt|tpf]
+    python bench.py --planes | --critical N
 """
 from __future__ import annotations
 

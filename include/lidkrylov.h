@@ -56,9 +56,6 @@ extern "C" {
 #define LC_LEARNED 2 /* network guess of the first correction, then LC_MIXED  */
                      /* passes (needs lc_set_net; plain fallback, see below) */
 
-/* Pressure-correction Poisson solvers. */
-#define LC_POISSON_TP 0 /* full tensor-product factorization (default)        */
-
 typedef struct lc_ctx lc_ctx;
 typedef struct lc_net lc_net;
 

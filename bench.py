@@ -229,12 +229,15 @@ PAPER_TABLE3_A0 = {100: (1963.74, 0.575370), 150: (1938.98, 0.581315), 200: (193
 
 
 # algorithmic HBM bytes per cell of the plane kernels of one projection with its potential:
-# right side (two components in, one cell value out: 24), mode-space scaling (16),
-# correction (two components and phi in, three components out: 48), prefix sums (16)
+# right side (two components in, one cell value out: 24), mode-space scaling (16; on the
+# TPT route only the y-z planes take it, the planes containing x solve by the tridiagonal
+# pass instead), correction (two components and phi in, three components out: 48), prefix
+# sums (16)
 PLANE_BYTES_PER_CELL = 24.0 + 16.0 + 48.0 + 16.0
+PLANE_BYTES_PER_CELL_TPT = (2 * (PLANE_BYTES_PER_CELL - 16.0) + PLANE_BYTES_PER_CELL) / 3.0
 
 
-def time_planes(ctx, torch, v, steps=10):
+def time_planes(ctx, torch, v, steps=10, route="tpt"):
     """Plane projections v1, v2, v3 with their potentials (eqs. 11-17) of one input:
     per family the mean wall time of a call (stream synchronized per call), then the
     per-class HIP-event times of one profiled pass over the three families."""
@@ -264,19 +267,21 @@ def time_planes(ctx, torch, v, steps=10):
     res["classes_ms_per_projection"] = {k: ms / calls for k, (ms, _) in prof.items()}
     if "planes" in prof:
         ms = prof["planes"][0] / calls
-        gbs = PLANE_BYTES_PER_CELL * n3 / (ms * 1e-3) / 1e9
-        res["plane_kernels"] = {"ms_per_projection": ms, "algorithmic_bytes": PLANE_BYTES_PER_CELL * n3,
+        per_cell = PLANE_BYTES_PER_CELL_TPT if route == "tpt" else PLANE_BYTES_PER_CELL
+        gbs = per_cell * n3 / (ms * 1e-3) / 1e9
+        res["plane_kernels"] = {"ms_per_projection": ms, "algorithmic_bytes": per_cell * n3,
                                 "GB/s": gbs, "frac_hbm": gbs / PEAK_HBM_GBS}
     return res
 
 
-def planes_run(n, lk, torch, steps):
+def planes_run(n, lk, torch, steps, route):
     import synth
     ctx = lk.Context(n, n, n)
     ctx.set_stretching("tanh", TANH_RATIO)
+    ctx.set_poisson_method(route)
     v = torch.from_numpy(synth.random_velocity(n, n, n, 1)).cuda()
     log(f"[planes] {n}^3 tanh-{TANH_RATIO:g}: {steps} calls per family")
-    res = time_planes(ctx, torch, v, steps)
+    res = time_planes(ctx, torch, v, steps, route)
     res = {"metric": "plane projections with potentials (eqs. 11-17) per second", "grid": [n, n, n],
            "stretching": "tanh", "ratio": TANH_RATIO, **res}
     print(json.dumps(res), flush=True)
@@ -337,7 +342,7 @@ def main():
         return
     if a.planes:
         torch.cuda.set_device(0)
-        planes_run(a.size, lk, torch, a.steps)
+        planes_run(a.size, lk, torch, a.steps, a.poisson)
         return
     n = a.size
     torch.cuda.set_device(0)
@@ -419,7 +424,7 @@ def main():
     log("[bench] Arnoldi cycle (m=30, k=6, one restart)")
     arnoldi = time_arnoldi(ctx, lk, torch)
     log(f"[bench] Arnoldi: {arnoldi['steps_per_s']:.1f} steps/s ({arnoldi['vectors']} vectors)")
-    planes = time_planes(ctx, torch, inputs[0])
+    planes = time_planes(ctx, torch, inputs[0], route=a.poisson)
     log(f"[bench] plane projections: {planes['gpu_ms_per_projection']:.3f} ms GPU time each")
     out = {
         "metric": "Krylov vectors/s to 1e-8 rel. residual at 200^3 (plain/mixed/learned); % HBM peak",

@@ -159,7 +159,8 @@ hipError_t launch_zero_walls(double* vel, int nx, int ny, int nz, hipStream_t st
 
 // ---------------------------------------------------- TPT tridiagonal x step
 // For every x-line (k, j) of a (y, z)-transformed cell field: (D_x G_x + ly[j] + lz[k]) out
-// = in; the line (zk, zj) is the singular one (solution with zero d-weighted mean).
+// = in (a null array adds nothing); the lines with j = zj and k = zk are the singular ones
+// (solutions with zero d-weighted mean), a negative index matching every j or k.
 // Lines of up to tridiag_x_max() cells.
 int tridiag_x_max();
 hipError_t launch_tridiag_x(const GridDev& g, const double* ly, const double* lz, int zj, int zk, const double* in,

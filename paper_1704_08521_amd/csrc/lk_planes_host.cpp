@@ -1,5 +1,7 @@
 // C ABI of the plane projections (Section 4, eqs. 11-17): the plane Poisson problems
-// reuse the per-axis transforms of the pressure solver along the two in-plane axes.
+// reuse the per-axis transforms of the pressure solver along the two in-plane axes, or,
+// for the planes containing x with the TPT route selected, one transform pair and the
+// tridiagonal x pass.
 #include <hip/hip_runtime.h>
 
 #include "lk_ctx.h"
@@ -72,6 +74,23 @@ extern "C" int lc_plane_project(lc_ctx* c, const double* v, int which, double* o
   const int a = kA[which], b = kB[which], nrm = kN[which];
   hipStream_t s = c->stream;
   KLAUNCH(c, LC_K_PLANES, launch_plane_rhs(c->g, which, v, c->r, s));
+  if (a == 0 && c->poisson_method == LC_POISSON_TPT && c->nx <= tridiag_x_max()) {
+    // planes containing x (P = 1, 3): transform along the other in-plane axis, one
+    // tridiagonal solve per x-line shifted by that axis's eigenvalues, transform back
+    const AxisModes& B = c->modes[b];
+    const double* lb = B.sym ? B.lam_s : B.lam;
+    rc = axis_pass(c, b, true, c->r, c->t1);
+    if (rc) return rc;
+    KLAUNCH(c, LC_K_TRIDIAG,
+            launch_tridiag_x(c->g, b == 1 ? lb : nullptr, b == 2 ? lb : nullptr, b == 1 ? c->zero_mode[1] : -1,
+                             b == 2 ? c->zero_mode[2] : -1, c->t1, c->t2, s));
+    rc = axis_pass(c, b, false, c->t2, c->phi);
+    if (rc) return rc;
+    KLAUNCH(c, LC_K_PLANES, launch_plane_correct(c->g, which, v, c->phi, out, s));
+    if (psi) KLAUNCH(c, LC_K_PLANES, launch_plane_potential(c->g, which, out, psi, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    return LC_OK;
+  }
   // forward along a then b, scale, backward along b then a
   rc = axis_pass(c, a, true, c->r, c->t1);
   if (!rc) rc = axis_pass(c, b, true, c->t1, c->t2);

@@ -10,7 +10,8 @@
 // lane then recovers its interior rows.  The line whose shift is zero (the zero modes of
 // y and z) is singular: its first equation is replaced by phi_0 = 0 and the solution is
 // re-centred to zero d-weighted mean, which sets the constant mode to zero as the
-// transform route does.
+// transform route does.  The plane projections use the same pass with one shift array
+// null (adding nothing) and a negative zero-mode index matching every index.
 #include <hip/hip_runtime.h>
 
 #include "lk_device.h"
@@ -39,8 +40,8 @@ __global__ void __launch_bounds__(64 * kTriLinesPerBlock) k_tridiag_x(
   const long line = (long)blockIdx.x * kTriLinesPerBlock + (long)(threadIdx.x >> 6);
   if (line >= lines) return;  // uniform per wave
   const int j = (int)(line % ny), k = (int)(line / ny);
-  const double shift = ly[j] + lz[k];
-  const bool sing = (j == zj) && (k == zk);
+  const double shift = (ly ? ly[j] : 0.0) + (lz ? lz[k] : 0.0);
+  const bool sing = (zj < 0 || j == zj) && (zk < 0 || k == zk);
   const int P = (n + M - 1) / M;  // segments (lanes in use)
   const int s0 = lane * M;
   const int L = (lane < P) ? min(M, n - s0) : 0;  // rows of this lane's segment

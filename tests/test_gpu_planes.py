@@ -1,7 +1,8 @@
 """GPU parity of the plane projections and their potentials (Section 4, eqs. 11-17).
 
 Small grids: element-wise against the dense per-plane oracle (oracle.planes), out and
-psi to 1e-11 of their largest value (two transform pairs instead of three, so the bound
+psi to 1e-11 of their largest value, on the default route (the planes containing x by the
+tridiagonal x pass) and on the transform route (two transform pairs instead of three, so the bound
 of the 3D Poisson solve applies).  Grids on all three transform variants: matrix cores
 (mirror-symmetric axes up to 256 cells), folded half-size and full matrices (seeded
 random widths).  Larger grids (200^3, 45 x 30 x 61), where the dense oracle is out of
@@ -96,6 +97,24 @@ def test_plane_projection_asymmetric_grids(case, which):
     dims, sym = case
     c, g = ctx_faces(dims, sym)
     check_against_oracle(c, g, which, 80 + which)
+
+
+@pytest.mark.parametrize("which", [1, 3])
+@pytest.mark.parametrize("case", [SMALL[1], SMALL[2]])
+def test_plane_projection_transform_route(case, which):
+    # the planes containing x solve by the tridiagonal x pass on the default (TPT) route;
+    # with the TPF route selected they use the x transforms instead
+    dims, kind = case
+    c, g = ctx_kind(*dims, kind)
+    c.set_poisson_method("tpf")
+    check_against_oracle(c, g, which, 75 + which)
+
+
+@pytest.mark.parametrize("which", [1, 3])
+def test_plane_projection_transform_route_asymmetric(which):
+    c, g = ctx_faces(*ASYM[1])
+    c.set_poisson_method("tpf")
+    check_against_oracle(c, g, which, 85 + which)
 
 
 def interior_potential(g, which, rng):

@@ -1,8 +1,8 @@
 """Krylov vectors per second at 200^3 on one MI355X.
 
 One step = one Krylov vector (eqs. 8-10): the linearized momentum stencil, the
-SIMPLE projection (divergence, tensor-product pressure-correction solve (TPT for
-FP64 unless --poisson tpf), velocity/pressure correction, divergence certificate) to a relative divergence
+SIMPLE projection (divergence, tensor-product pressure-correction solve (TPT unless
+--poisson tpf), velocity/pressure correction, divergence certificate) to a relative divergence
 residual rho <= 1e-8, on a 200^3 tanh-stretched grid (centre/wall spacing 10),
 Re = 1900, lid along x.  Inputs are seeded (SplitMix64) and resident in HBM
 before the timed region.  Three forms: plain FP64, mixed (FP32 solves inside
@@ -50,8 +50,8 @@ def parse():
                          "on the sine grid of eq. 5, lid along x (Newton continuation, then the secant "
                          "driver lc_critical_re); one JSON line")
     ap.add_argument("--poisson", choices=("tpt", "tpf"), default="tpt",
-                    help="pressure-solve route of the FP64 passes (transforms along y, z with tridiagonal "
-                         "solves along x, or transforms along x, y, z)")
+                    help="pressure-solve route (transforms along y, z with tridiagonal solves along x, "
+                         "or transforms along x, y, z)")
     ap.add_argument("--planes", action="store_true",
                     help="instead of the Krylov-vector benchmark: only the plane projections and potentials "
                          "(eqs. 11-17) at --size^3; one JSON line")

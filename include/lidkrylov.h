@@ -126,13 +126,13 @@ int lc_residual(lc_ctx* ctx, const double* U, double* R);
  * receives (host) the volume-weighted norm sqrt(sum V r^2). */
 int lc_divergence(lc_ctx* ctx, const double* v, double* r, double* vnorm);
 
-/* Pressure-solve route of the FP64 passes (Section 3: the paper's TPT and TPF
- * tensor-product solvers).  LC_POISSON_TPT (default): mode transforms along y and z
- * and, along x, one tridiagonal solve per line (a partition method: per-lane segment
- * elimination, cyclic reduction across the lanes), for nx up to 1024 (larger nx uses
- * TPF).  LC_POISSON_TPF: mode transforms along x, y and z and a division by the
- * eigenvalue sums.  Both give the same solution up to rounding; FP32 solves (the mixed
- * form) always use TPF.  LC_EINVAL for an unknown method. */
+/* Pressure-solve route (Section 3: the paper's TPT and TPF tensor-product solvers),
+ * for the FP64 and FP32 solves alike.  LC_POISSON_TPT (default): mode transforms along
+ * y and z and, along x, one tridiagonal solve per line (a partition method: per-lane
+ * segment elimination, cyclic reduction across the lanes), for nx up to 1024 (larger nx
+ * uses TPF).  LC_POISSON_TPF: mode transforms along x, y and z and a division by the
+ * eigenvalue sums.  Both give the same solution up to rounding.  LC_EINVAL for an
+ * unknown method. */
 #define LC_POISSON_TPF 0
 #define LC_POISSON_TPT 1
 int lc_set_poisson_method(lc_ctx* ctx, int method);

@@ -98,8 +98,8 @@ class Context:
         self._check(self.lib.lc_set_lid(self._h, float(alpha)))
 
     def set_poisson_method(self, method):
-        """Pressure-solve route of the FP64 passes: "tpt" (the default: transforms along
-        y, z and tridiagonal solves along x) or "tpf" (transforms along x, y, z)."""
+        """Pressure-solve route (FP64 and FP32 solves): "tpt" (the default: transforms
+        along y, z and tridiagonal solves along x) or "tpf" (transforms along x, y, z)."""
         m = {"tpf": 0, "tpt": 1}[method]
         self._check(self.lib.lc_set_poisson_method(self._h, m))
 

@@ -289,7 +289,7 @@ int tp_solve(lc_ctx* c, const T* r, T* phi, T* t1, T* t2) {
   hipStream_t s = c->stream;
   const int n_yz = ny * nz, n_xz = nx * nz;
   const double* nul = nullptr;
-  if constexpr (sizeof(T) == sizeof(double)) {
+  {
     if (c->poisson_method == LC_POISSON_TPT && nx <= tridiag_x_max()) {
       // TPT: forward y and z, tridiagonal solves along x, backward z and y
       if (Y.mf)
@@ -309,7 +309,7 @@ int tp_solve(lc_ctx* c, const T* r, T* phi, T* t1, T* t2) {
         KLAUNCH(c, LC_K_TP_Z, launch_tp_left<T>(nz, (int)pl, nz, pick(Z, 0), t1, t2, (int)pl, 0, pl, nul, nul, nul, 1, 0,
                                                 0, 0, s));
       KLAUNCH(c, LC_K_TRIDIAG,
-              launch_tridiag_x(c->g, lams(Y), lams(Z), c->zero_mode[1], c->zero_mode[2], t2, t1, s));
+              launch_tridiag_x<T>(c->g, lams(Y), lams(Z), c->zero_mode[1], c->zero_mode[2], t2, t1, s));
       if (Z.mf)
         KLAUNCH(c, LC_K_TP_Z, launch_mfu_left<T>(nz, (int)pl, packs(Z, 2), packs(Z, 3), t1, t2, (int)pl, 0, pl, nul,
                                                  nul, nul, 1, 0, 0, 0, s));

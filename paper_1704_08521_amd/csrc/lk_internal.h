@@ -163,8 +163,9 @@ hipError_t launch_zero_walls(double* vel, int nx, int ny, int nz, hipStream_t st
 // (solutions with zero d-weighted mean), a negative index matching every j or k.
 // Lines of up to tridiag_x_max() cells.
 int tridiag_x_max();
-hipError_t launch_tridiag_x(const GridDev& g, const double* ly, const double* lz, int zj, int zk, const double* in,
-                            double* out, hipStream_t st);
+template <typename T>
+hipError_t launch_tridiag_x(const GridDev& g, const double* ly, const double* lz, int zj, int zk, const T* in, T* out,
+                            hipStream_t st);
 
 // ---------------------------------------------------- plane projections
 // P = 1 keeps (u, w) (planes y = const), 2 keeps (v, w) (x = const), 3 keeps (u, v)

@@ -82,7 +82,7 @@ extern "C" int lc_plane_project(lc_ctx* c, const double* v, int which, double* o
     rc = axis_pass(c, b, true, c->r, c->t1);
     if (rc) return rc;
     KLAUNCH(c, LC_K_TRIDIAG,
-            launch_tridiag_x(c->g, b == 1 ? lb : nullptr, b == 2 ? lb : nullptr, b == 1 ? c->zero_mode[1] : -1,
+            launch_tridiag_x<double>(c->g, b == 1 ? lb : nullptr, b == 2 ? lb : nullptr, b == 1 ? c->zero_mode[1] : -1,
                              b == 2 ? c->zero_mode[2] : -1, c->t1, c->t2, s));
     rc = axis_pass(c, b, false, c->t2, c->phi);
     if (rc) return rc;

@@ -22,46 +22,54 @@ namespace {
 
 constexpr int kTriLinesPerBlock = 4;  // one wave per line
 
-// 1 / a to FP64 accuracy: the hardware reciprocal refined by two Newton steps
-__device__ __forceinline__ double rcp64(double a) {
+// 1 / a to the type's accuracy: the hardware reciprocal refined by Newton steps (two in
+// FP64, one in FP32)
+__device__ __forceinline__ double rcpx(double a) {
   double y = __builtin_amdgcn_rcp(a);
   double e = fma(-a, y, 1.0);
   y = fma(e, y, y);
   e = fma(-a, y, 1.0);
   return fma(e, y, y);
 }
+__device__ __forceinline__ float rcpx(float a) {
+  const float y = __builtin_amdgcn_rcpf(a);
+  return fmaf(fmaf(-a, y, 1.0f), y, y);
+}
 
-template <int M>
+template <typename T, int M>
 __global__ void __launch_bounds__(64 * kTriLinesPerBlock) k_tridiag_x(
     const double* __restrict__ rd, const double* __restrict__ rdd, const double* __restrict__ dx, int n, int ny,
     long lines, const double* __restrict__ ly, const double* __restrict__ lz, int zj, int zk,
-    const double* __restrict__ in, double* __restrict__ out) {
+    const T* __restrict__ in, T* __restrict__ out) {
   const int lane = (int)(threadIdx.x & 63);
   const long line = (long)blockIdx.x * kTriLinesPerBlock + (long)(threadIdx.x >> 6);
   if (line >= lines) return;  // uniform per wave
   const int j = (int)(line % ny), k = (int)(line / ny);
-  const double shift = (ly ? ly[j] : 0.0) + (lz ? lz[k] : 0.0);
+  const T shift = (T)((ly ? ly[j] : 0.0) + (lz ? lz[k] : 0.0));
   const bool sing = (zj < 0 || j == zj) && (zk < 0 || k == zk);
   const int P = (n + M - 1) / M;  // segments (lanes in use)
   const int s0 = lane * M;
   const int L = (lane < P) ? min(M, n - s0) : 0;  // rows of this lane's segment
-  const double* src = in + (size_t)line * n;
-  // the segment's rows: a x_{r-1} + b x_r + c x_{r+1} = d (identity rows beyond L)
-  double ra[M], rb[M], rc[M], rv[M];
+  const T* src = in + (size_t)line * n;
+  // the segment's rows: a x_{r-1} + b x_r + c x_{r+1} = d (identity rows beyond L); the
+  // coefficients are formed in FP64 and rounded to T
+  T ra[M], rb[M], rc[M], rv[M];
 #pragma unroll
   for (int t = 0; t < M; ++t) {
     const int r = s0 + t;
-    double a = 0.0, b = 1.0, c = 0.0, d = 0.0;
+    T a = 0, b = 1, c = 0, d = 0;
     if (t < L) {
-      a = (r > 0) ? rdd[r] * rd[r] : 0.0;
-      c = (r + 1 < n) ? rdd[r + 1] * rd[r] : 0.0;
-      b = shift - (a + c);
+      const double a64 = (r > 0) ? rdd[r] * rd[r] : 0.0;
+      const double c64 = (r + 1 < n) ? rdd[r + 1] * rd[r] : 0.0;
+      a = (T)a64;
+      c = (T)c64;
+      b = shift - (T)(a64 + c64);
       d = src[r];
       if (sing && r == 0) {
-        a = 0.0;
-        b = 1.0;
-        c = 0.0;
-        d = 0.0;
+        a = 0;
+        b = 1;
+        c = 0;
+        d = 0;
       }
     }
     ra[t] = a;
@@ -72,24 +80,24 @@ __global__ void __launch_bounds__(64 * kTriLinesPerBlock) k_tridiag_x(
   // interior rows 0 .. q-1 in terms of the two segment ends z_{p-1} (previous lane's last
   // row) and z_p (own last row): x = Y - V z_{p-1} - W z_p
   const int q = L - 1;
-  double Y[M], V[M], W[M], cp[M];
+  T Y[M], V[M], W[M], cp[M];
 #pragma unroll
   for (int i = 0; i < M; ++i) {
-    Y[i] = 0.0;
-    V[i] = 0.0;
-    W[i] = 0.0;
-    cp[i] = 0.0;
+    Y[i] = 0;
+    V[i] = 0;
+    W[i] = 0;
+    cp[i] = 0;
   }
 #pragma unroll
   for (int i = 0; i < M - 1; ++i) {
     if (i < q) {
-      const double sub = (i > 0) ? ra[i] : 0.0;
-      const double den = rb[i] - ((i > 0) ? sub * cp[i - 1] : 0.0);
-      const double r = rcp64(den);
-      cp[i] = ((i < q - 1) ? rc[i] : 0.0) * r;
-      Y[i] = (rv[i] - ((i > 0) ? sub * Y[i - 1] : 0.0)) * r;
-      V[i] = (((i == 0) ? ra[0] : 0.0) - ((i > 0) ? sub * V[i - 1] : 0.0)) * r;
-      W[i] = (((i == q - 1) ? rc[i] : 0.0) - ((i > 0) ? sub * W[i - 1] : 0.0)) * r;
+      const T sub = (i > 0) ? ra[i] : T(0);
+      const T den = rb[i] - ((i > 0) ? sub * cp[i - 1] : T(0));
+      const T r = rcpx(den);
+      cp[i] = ((i < q - 1) ? rc[i] : T(0)) * r;
+      Y[i] = (rv[i] - ((i > 0) ? sub * Y[i - 1] : T(0))) * r;
+      V[i] = (((i == 0) ? ra[0] : T(0)) - ((i > 0) ? sub * V[i - 1] : T(0))) * r;
+      W[i] = (((i == q - 1) ? rc[i] : T(0)) - ((i > 0) ? sub * W[i - 1] : T(0))) * r;
     }
   }
 #pragma unroll
@@ -102,15 +110,15 @@ __global__ void __launch_bounds__(64 * kTriLinesPerBlock) k_tridiag_x(
   }
   // the segment's first row and the row before its last, as (Y, V, W) of the ends; with no
   // interior rows the first row is z_p itself and the row before the last is z_{p-1}
-  double Yf = 0.0, Vf = 0.0, Wf = 0.0, Yl = 0.0, Vl = 0.0, Wl = 0.0;
-  double ae = 0.0, be = 1.0, ce = 0.0, de = 0.0;
+  T Yf = 0, Vf = 0, Wf = 0, Yl = 0, Vl = 0, Wl = 0;
+  T ae = 0, be = 1, ce = 0, de = 0;
   if (q >= 1) {
     Yf = Y[0];
     Vf = V[0];
     Wf = W[0];
   } else if (q == 0) {
-    Wf = -1.0;
-    Vl = -1.0;
+    Wf = -1;
+    Vl = -1;
   }
 #pragma unroll
   for (int i = 0; i < M; ++i) {
@@ -127,8 +135,8 @@ __global__ void __launch_bounds__(64 * kTriLinesPerBlock) k_tridiag_x(
     }
   }
   // the last row's equation in the segment ends: al z_{p-1} + bt z_p + ga z_{p+1} = dl
-  const double Yn = __shfl_down(Yf, 1), Vn = __shfl_down(Vf, 1), Wn = __shfl_down(Wf, 1);
-  double al = 0.0, bt = 1.0, ga = 0.0, dl = 0.0;
+  const T Yn = __shfl_down(Yf, 1), Vn = __shfl_down(Vf, 1), Wn = __shfl_down(Wf, 1);
+  T al = 0, bt = 1, ga = 0, dl = 0;
   if (L > 0) {
     al = -ae * Vl;
     bt = be - ae * Wl - ce * Vn;
@@ -137,19 +145,18 @@ __global__ void __launch_bounds__(64 * kTriLinesPerBlock) k_tridiag_x(
   }
   // cyclic reduction across the lanes (identity rows beyond P couple to nothing)
   for (int st = 1; st < P; st <<= 1) {
-    const double rbt = rcp64(bt);
-    const double am = __shfl_up(al, st), gm = __shfl_up(ga, st), dm = __shfl_up(dl, st), rm = __shfl_up(rbt, st);
-    const double ap = __shfl_down(al, st), gp = __shfl_down(ga, st), dp = __shfl_down(dl, st),
-                 rp = __shfl_down(rbt, st);
-    double an = 0.0, gn = 0.0, bn = bt, dn = dl;
+    const T rbt = rcpx(bt);
+    const T am = __shfl_up(al, st), gm = __shfl_up(ga, st), dm = __shfl_up(dl, st), rm = __shfl_up(rbt, st);
+    const T ap = __shfl_down(al, st), gp = __shfl_down(ga, st), dp = __shfl_down(dl, st), rp = __shfl_down(rbt, st);
+    T an = 0, gn = 0, bn = bt, dn = dl;
     if (lane >= st) {
-      const double k1 = al * rm;
+      const T k1 = al * rm;
       an = -am * k1;
       bn -= gm * k1;
       dn -= dm * k1;
     }
     if (lane + st < 64) {
-      const double k2 = ga * rp;
+      const T k2 = ga * rp;
       gn = -gp * k2;
       bn -= ap * k2;
       dn -= dp * k2;
@@ -159,12 +166,12 @@ __global__ void __launch_bounds__(64 * kTriLinesPerBlock) k_tridiag_x(
     ga = gn;
     dl = dn;
   }
-  const double z = dl / bt;
-  const double zu = __shfl_up(z, 1);  // every lane takes part in the shuffle
-  const double zl = (lane > 0) ? zu : 0.0;
-  double x[M];
+  const T z = dl / bt;
+  const T zu = __shfl_up(z, 1);  // every lane takes part in the shuffle
+  const T zl = (lane > 0) ? zu : T(0);
+  T x[M];
 #pragma unroll
-  for (int i = 0; i < M; ++i) x[i] = (i < q) ? Y[i] - V[i] * zl - W[i] * z : (i == q ? z : 0.0);
+  for (int i = 0; i < M; ++i) x[i] = (i < q) ? Y[i] - V[i] * zl - W[i] * z : (i == q ? z : T(0));
   if (sing) {  // uniform per wave
     double sw = 0.0, swx = 0.0;
 #pragma unroll
@@ -172,15 +179,15 @@ __global__ void __launch_bounds__(64 * kTriLinesPerBlock) k_tridiag_x(
       if (i < L) {
         const double w = dx[s0 + i];
         sw += w;
-        swx += w * x[i];
+        swx += w * (double)x[i];
       }
     }
     // (the wave sums are complete in lane 0: broadcast them)
     const double mean = __shfl(wave_sum(swx), 0) / __shfl(wave_sum(sw), 0);
 #pragma unroll
-    for (int i = 0; i < M; ++i) x[i] -= mean;
+    for (int i = 0; i < M; ++i) x[i] -= (T)mean;
   }
-  double* dst = out + (size_t)line * n;
+  T* dst = out + (size_t)line * n;
 #pragma unroll
   for (int i = 0; i < M; ++i)
     if (i < L) dst[s0 + i] = x[i];
@@ -190,25 +197,31 @@ __global__ void __launch_bounds__(64 * kTriLinesPerBlock) k_tridiag_x(
 
 int tridiag_x_max() { return 64 * 16; }
 
-hipError_t launch_tridiag_x(const GridDev& g, const double* ly, const double* lz, int zj, int zk, const double* in,
-                            double* out, hipStream_t st) {
+template <typename T>
+hipError_t launch_tridiag_x(const GridDev& g, const double* ly, const double* lz, int zj, int zk, const T* in, T* out,
+                            hipStream_t st) {
   const int n = g.x.n, ny = g.y.n, nz = g.z.n;
   const long lines = (long)ny * nz;
   const dim3 grid((unsigned)((lines + kTriLinesPerBlock - 1) / kTriLinesPerBlock)), block(64 * kTriLinesPerBlock);
   const double *rd = g.x.rd, *rdd = g.x.rdd, *dx = g.x.d;
   if (n <= 64)
-    hipLaunchKernelGGL(k_tridiag_x<1>, grid, block, 0, st, rd, rdd, dx, n, ny, lines, ly, lz, zj, zk, in, out);
+    hipLaunchKernelGGL((k_tridiag_x<T, 1>), grid, block, 0, st, rd, rdd, dx, n, ny, lines, ly, lz, zj, zk, in, out);
   else if (n <= 128)
-    hipLaunchKernelGGL(k_tridiag_x<2>, grid, block, 0, st, rd, rdd, dx, n, ny, lines, ly, lz, zj, zk, in, out);
+    hipLaunchKernelGGL((k_tridiag_x<T, 2>), grid, block, 0, st, rd, rdd, dx, n, ny, lines, ly, lz, zj, zk, in, out);
   else if (n <= 256)
-    hipLaunchKernelGGL(k_tridiag_x<4>, grid, block, 0, st, rd, rdd, dx, n, ny, lines, ly, lz, zj, zk, in, out);
+    hipLaunchKernelGGL((k_tridiag_x<T, 4>), grid, block, 0, st, rd, rdd, dx, n, ny, lines, ly, lz, zj, zk, in, out);
   else if (n <= 512)
-    hipLaunchKernelGGL(k_tridiag_x<8>, grid, block, 0, st, rd, rdd, dx, n, ny, lines, ly, lz, zj, zk, in, out);
+    hipLaunchKernelGGL((k_tridiag_x<T, 8>), grid, block, 0, st, rd, rdd, dx, n, ny, lines, ly, lz, zj, zk, in, out);
   else if (n <= 1024)
-    hipLaunchKernelGGL(k_tridiag_x<16>, grid, block, 0, st, rd, rdd, dx, n, ny, lines, ly, lz, zj, zk, in, out);
+    hipLaunchKernelGGL((k_tridiag_x<T, 16>), grid, block, 0, st, rd, rdd, dx, n, ny, lines, ly, lz, zj, zk, in, out);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
 }
+
+template hipError_t launch_tridiag_x<double>(const GridDev&, const double*, const double*, int, int, const double*,
+                                             double*, hipStream_t);
+template hipError_t launch_tridiag_x<float>(const GridDev&, const double*, const double*, int, int, const float*,
+                                            float*, hipStream_t);
 
 }  // namespace lk

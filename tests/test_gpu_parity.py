@@ -268,6 +268,8 @@ def test_poisson_solve_each_route(case, method):
     ref = poisson.PoissonFD(g).solve(r)
     phi = host(c.poisson_solve(dev(r.ravel()))).reshape(nz, ny, nx)
     assert rel(phi, ref) < 1e-11
+    phi32 = host(c.poisson_solve(dev(r.ravel()), precision=1)).reshape(nz, ny, nx)
+    assert rel(phi32, ref) < 1e-4
     v = synth.random_velocity(nx, ny, nz, 6)
     vo, po, st = c.krylov_vector(dev(v), tol=1e-10)
     ref_v, ref_p = simple.Projector(g).krylov_vector(U, v, 700.0)
@@ -288,6 +290,8 @@ def test_poisson_solve_each_route_asymmetric_grids(case, method):
     ref = poisson.PoissonFD(g).solve(r)
     phi = host(c.poisson_solve(dev(r.ravel()))).reshape(nz, ny, nx)
     assert rel(phi, ref) < 1e-11
+    phi32 = host(c.poisson_solve(dev(r.ravel()), precision=1)).reshape(nz, ny, nx)
+    assert rel(phi32, ref) < 1e-4
 
 
 @pytest.mark.parametrize("n", [1000, 300])

@@ -294,9 +294,10 @@ def test_poisson_solve_each_route_asymmetric_grids(case, method):
     assert rel(phi32, ref) < 1e-4
 
 
-@pytest.mark.parametrize("n", [1000, 300])
-def test_tpt_long_lines(n):
-    # x-lines beyond 256 cells (8 and 16 rows per lane) against TPF on a thin grid
+@pytest.mark.parametrize("n", [1000, 513, 300, 128, 100, 65])
+def test_tpt_line_lengths(n):
+    # every rows-per-lane instance of the tridiagonal pass (2 rows: 65-128 cells, 8: 257-512,
+    # 16: 513-1024; 1 and 4 are covered by the grids above) against TPF on a thin grid
     c, g, _ = ctx_for(n, 3, 4, "tanh")
     r = synth.random_cells(n, 3, 4, 17)
     V = g.volumes()

@@ -42,7 +42,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--size", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-sample", type=int, default=2, help="oracle Krylov vectors timed on the host")
+    ap.add_argument("--cpu-reps", type=int, default=3, help="timed oracle Krylov vectors (after one warm-up)")
     ap.add_argument("--train-steps", type=int, default=300, help="Adam steps of the learned guess (64^3 pairs)")
     ap.add_argument("--train-size", type=int, default=64)
     ap.add_argument("--critical", type=int, default=0, metavar="N",
@@ -196,31 +196,56 @@ def time_arnoldi(ctx, lk, torch, m=30, k=6):
     return {"m": m, "k": k, "restarts": 1, "vectors": nvec, "seconds": dt, "steps_per_s": nvec / dt}
 
 
-def cpu_baseline(n, sample):
-    """The oracle (numpy/scipy, float64) on the host cores: Krylov vectors/s."""
+def cpu_baseline(n, reps=3):
+    """The oracle (numpy/scipy, float64) on the host cores: Krylov vectors/s at n^3 and at
+    100^3 (one warm-up, then the median of `reps` timed vectors each), and the first
+    workload end to end at 16^3 (oracle Newton from rest to 1e-10, then ARPACK with 20
+    vectors for the 4 leading eigenvalues)."""
+    import statistics
     import numpy as np
     import synth
-    from oracle import simple
+    from oracle import eigen, simple
     from oracle.grid import Grid
+    from oracle.newton import Newton
     try:
         from threadpoolctl import threadpool_info
         threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
     except Exception:
         threads = os.cpu_count()
-    g = Grid.make(n, kind="tanh", ratio=TANH_RATIO)
-    P = simple.Projector(g)
-    U = synth.random_velocity(n, n, n, 1000)
-    U, _ = P.project(U)
-    U /= np.max(np.abs(U))
-    vs = [synth.random_velocity(n, n, n, s) for s in range(1, sample + 1)]
+
+    def vectors_per_s(m):
+        g = Grid.make(m, kind="tanh", ratio=TANH_RATIO)
+        P = simple.Projector(g)
+        U, _ = P.project(synth.random_velocity(m, m, m, 1000))
+        U /= np.max(np.abs(U))
+        times = []
+        for s in range(reps + 1):               # the first is the warm-up
+            v = synth.random_velocity(m, m, m, s + 1)
+            t0 = time.perf_counter()
+            P.krylov_vector(U, v, RE)
+            if s:
+                times.append(time.perf_counter() - t0)
+        return 1.0 / statistics.median(times), times
+
+    value, times = vectors_per_s(n)
+    out = {"value": value, "unit": "Krylov vectors/s", "cores": threads, "kind": "oracle",
+           "sample": f"1 warm-up + median of {reps} Krylov vectors at {n}^3 tanh-10, Re={RE:g} (numpy float64; "
+                     f"stencils single-threaded, transforms on {threads} BLAS threads)",
+           "seconds": times}
+    if n != 100:
+        v100, t100 = vectors_per_s(100)
+        out["at_100"] = {"value": v100, "unit": "Krylov vectors/s", "seconds": t100}
+    g = Grid.make(16)
     t0 = time.perf_counter()
-    for v in vs:
-        P.krylov_vector(U, v, RE)
-    dt = time.perf_counter() - t0
-    return {"value": sample / dt, "unit": "Krylov vectors/s", "cores": threads, "kind": "oracle",
-            "sample": f"{sample} Krylov vectors at {n}^3 tanh-10, Re={RE:g} (numpy float64; "
-                      f"stencils single-threaded, transforms on {threads} BLAS threads)",
-            "seconds": dt}
+    U, hist = Newton(g, 100.0, 0.0).solve(tol=1e-10)
+    t1 = time.perf_counter()
+    lam = eigen.arpack(g, U, 100.0, k=4, ncv=20, tol=1e-10)
+    t2 = time.perf_counter()
+    out["first_workload_16"] = {"newton_s": t1 - t0, "newton_steps": len(hist) - 1, "arnoldi_s": t2 - t1,
+                                "total_s": t2 - t0, "leading": [[float(z.real), float(z.imag)] for z in lam[:4]],
+                                "what": "16^3 uniform, Re=100, alpha=0: Newton (sparse direct) to |F| <= 1e-10, "
+                                        "then ARPACK (20 vectors) for 4 leading eigenvalues"}
+    return out
 
 
 # Table 3 of the paper (alpha = 0, sine grid of eq. 5): critical Re and frequency per grid
@@ -450,8 +475,8 @@ def main():
         "kernels": table,
     }
     if not a.no_cpu:
-        log(f"[bench] cpu baseline: {a.cpu_sample} oracle Krylov vectors at {n}^3")
-        out["cpu_baseline"] = cpu_baseline(n, a.cpu_sample)
+        log(f"[bench] cpu baseline: oracle Krylov vectors at {n}^3 and 100^3, first workload at 16^3")
+        out["cpu_baseline"] = cpu_baseline(n, a.cpu_reps)
     print(json.dumps(out), flush=True)
 
 

@@ -21,9 +21,10 @@
  * Execution: one context per stream; calls enqueue on the context's HIP stream
  * and return when their outputs are valid (convergence control reads scalar
  * reductions back to the host).  Contexts are not thread-safe.  Inputs and
- * outputs of one call must not alias unless a comment allows it.  The library
- * owns its scratch device memory (allocated in lc_create / lc_set_grid, freed in
- * lc_destroy).
+ * outputs of one call must not alias unless a comment allows it.  A context made by
+ * lc_create owns its scratch device memory (allocated in lc_create, lc_set_grid and
+ * on first use of a driver, freed in lc_destroy); one made by lc_create_in carves it
+ * from a caller-owned block sized by lc_workspace_query.
  *
  * Return codes: LC_OK = 0; LC_ENOTCONV = 1 (outputs valid, tolerance not met);
  * negative values are errors, the message is in lc_last_error().
@@ -43,7 +44,7 @@ extern "C" {
 #define LC_EINVAL (-1)  /* bad size, pointer, value, or non-finite input      */
 #define LC_ESTATE (-2)  /* grid, Re or base flow not set                      */
 #define LC_EHIP (-3)    /* HIP runtime error                                  */
-#define LC_ENOMEM (-4)  /* device allocation failed                           */
+#define LC_ENOMEM (-4)  /* device allocation failed, or caller workspace too small */
 
 /* Stretching kinds for lc_set_stretching. */
 #define LC_UNIFORM 0 /* x_i = i/N                                             */
@@ -82,6 +83,19 @@ const char* lc_last_error(const lc_ctx* ctx);
  * device.  The grid starts uniform, Re = 1, lid angle 0, base flow zero. */
 int lc_create(lc_ctx** out, int nx, int ny, int nz, void* hip_stream);
 int lc_destroy(lc_ctx* ctx);
+
+/* Caller-owned workspace.  lc_workspace_query gives the device bytes a context of an
+ * nx x ny x nz grid needs when every buffer it uses -- work fields, grid factors,
+ * viscous-step factors, reduction scratch, the critical-Re steady states, and the Krylov
+ * vectors of Newton with gmres_m <= m_max and Arnoldi with m <= m_max (0 <= m_max <= 400)
+ * -- comes from one block.  lc_create_in is lc_create with that block (device memory,
+ * 256-byte aligned, `bytes` long, owned by the caller and untouched by lc_destroy): the
+ * library then allocates no device memory of its own (small pinned host scalars and
+ * events only).  A call that needs more Krylov vectors than the block holds fails with
+ * LC_ENOMEM ("workspace too small"), as does lc_create_in when the block cannot hold the
+ * fixed buffers.  The block must outlive the context. */
+int lc_workspace_query(int nx, int ny, int nz, int m_max, size_t* bytes);
+int lc_create_in(lc_ctx** out, int nx, int ny, int nz, void* workspace, size_t bytes, void* hip_stream);
 int lc_set_stream(lc_ctx* ctx, void* hip_stream);
 
 /* Number of doubles in a packed velocity / a cell field. */
@@ -149,13 +163,14 @@ int lc_correct(lc_ctx* ctx, const double* w, const double* phi, double* v, doubl
 
 /* Divergence-free projection of w by the SIMPLE-like loop of Section 3:
  * v = w, p = 0; repeat { solve (D G) phi = D v; v -= G phi; p += phi } until
- * |D v|_V <= tol |D w|_V or max_iter passes.  v_out, p_out may be NULL-free
- * device buffers (velocity, cell).  stats may be NULL. */
+ * |D v|_V <= tol |D w|_V or max_iter passes.  v_out (velocity) is required; p_out
+ * (cell) may be NULL, and then no pressure is written (the Krylov drivers use the
+ * velocity only).  Neither may alias w.  stats may be NULL. */
 int lc_project(lc_ctx* ctx, const double* w, double* v_out, double* p_out,
                int precision, double tol, int max_iter, lc_stats* stats);
 
-/* The next Krylov vector (eqs. 8-10): v_out = P(L_U v_in), p_out its pressure,
- * by lc_jacobian_apply followed by lc_project. */
+/* The next Krylov vector (eqs. 8-10): v_out = P(L_U v_in), p_out its pressure (may be
+ * NULL), by lc_jacobian_apply followed by lc_project. */
 int lc_krylov_vector(lc_ctx* ctx, const double* v_in, double* v_out, double* p_out,
                      int precision, double tol, int max_iter, lc_stats* stats);
 
@@ -223,6 +238,44 @@ int lc_newton_step(lc_ctx* ctx, double lin_tol, int gmres_m, long max_vectors, i
 int lc_arnoldi_leading(lc_ctx* ctx, int k, int m, double tol, int max_restarts, unsigned long long seed,
                        int precision, double proj_tol, double* eig_re, double* eig_im, double* resid,
                        double* vec_re, double* vec_im, int* n_out, long* n_vectors);
+
+/* ------------------------------------ Stokes-preconditioned Krylov vectors */
+
+/* The comparison variant of Section 3: Krylov vectors preconditioned by a time step
+ * whose viscous part is implicit (Stokes preconditioning, the paper's refs. [35-37]).
+ *
+ * Viscous step: u = (I/dt - Re^-1 Lap_0)^-1 f, with Lap_0 the vector Laplacian of
+ * eq. 2 with homogeneous wall values (the operator of lc_jacobian_apply's viscous
+ * term), solved exactly per velocity component by a tensor-product factorization of
+ * its 1D Dirichlet factors (faces along the component's own axis, cells along the
+ * others).  dt > 0; dt = INFINITY gives the pure Stokes operator -Re^-1 Lap_0.
+ * f, u: velocity (device), distinct; wall-normal faces of f are ignored, those of u are
+ * zero.  LC_EINVAL for dt <= 0 or bad pointers.  The first call on a grid builds the
+ * factors (library-owned device memory, about 2.5 (n+1)^2 doubles per axis). */
+int lc_viscous_solve(lc_ctx* ctx, const double* f, double* u, double dt);
+
+/* Stokes step: u = P (I/dt - Re^-1 Lap_0)^-1 f, the viscous step followed by the
+ * divergence-free projection of lc_project (precision, tol, max_iter, stats as there;
+ * LC_ENOTCONV likewise).  As a right preconditioner M^-1 of the Newton system it keeps
+ * the solutions of (P L_U) d = F: M^-1 maps the divergence-free space onto itself and is
+ * invertible there (P (I/dt - Re^-1 Lap_0)^-1 P is symmetric definite in the face-volume
+ * inner product). */
+int lc_stokes_step(lc_ctx* ctx, const double* f, double* u, double dt, int precision, double tol, int max_iter,
+                   lc_stats* stats);
+
+/* Stokes-preconditioned Krylov vector: out = P (I/dt - Re^-1 Lap_0)^-1 P L_U v, the
+ * time-stepper form of the next Krylov vector (lc_krylov_vector followed by
+ * lc_stokes_step).  Its eigenvalues are not those of eq. 7; Newton corrections solved on
+ * it are.  v, out: velocity, distinct.  stats: those of the second projection. */
+int lc_stokes_vector(lc_ctx* ctx, const double* v, double* out, double dt, int precision, double tol, int max_iter,
+                     lc_stats* stats);
+
+/* Newton preconditioning: dt > 0 (or INFINITY) makes lc_newton_step solve
+ * (P L_U) M^-1 y = F with M^-1 = the Stokes step of time step dt and take d = M^-1 y
+ * (right preconditioning: the residual GMRES and BiCGstab(2) minimise is the true one);
+ * dt = 0 (the default) solves on the SIMPLE Krylov vectors alone.  Each preconditioned
+ * Krylov vector costs one viscous step and two projections more. */
+int lc_set_stokes_precond(lc_ctx* ctx, double dt);
 
 /* ------------------------------------------------- critical Reynolds number */
 

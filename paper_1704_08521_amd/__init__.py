@@ -23,7 +23,10 @@ def _torch():
 class Context:
     """One grid, one Reynolds number / lid, one base flow, on one HIP stream."""
 
-    def __init__(self, nx: int, ny: int | None = None, nz: int | None = None, stream=None):
+    def __init__(self, nx: int, ny: int | None = None, nz: int | None = None, stream=None, workspace=None):
+        """workspace: None (the library allocates its device memory), or a contiguous CUDA
+        tensor of at least ``Context.workspace_bytes(nx, ny, nz, m_max)`` bytes that holds all of
+        it (kept referenced by the context)."""
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("lidkrylov needs a GPU (torch.cuda.is_available() is False)")
@@ -35,7 +38,15 @@ class Context:
         s = stream if stream is not None else torch.cuda.current_stream()
         self.stream = s
         h = C.c_void_p()
-        rc = self.lib.lc_create(C.byref(h), nx, ny, nz, C.c_void_p(s.cuda_stream))
+        if workspace is None:
+            rc = self.lib.lc_create(C.byref(h), nx, ny, nz, C.c_void_p(s.cuda_stream))
+        else:
+            if not workspace.is_cuda or not workspace.is_contiguous():
+                raise ValueError("workspace: need a contiguous CUDA tensor")
+            nbytes = workspace.numel() * workspace.element_size()
+            rc = self.lib.lc_create_in(C.byref(h), nx, ny, nz, C.c_void_p(workspace.data_ptr()), C.c_size_t(nbytes),
+                                       C.c_void_p(s.cuda_stream))
+        self.workspace = workspace
         if rc != 0:
             raise LidKrylovError(rc, self.lib.lc_last_error(None).decode())
         self._h = h
@@ -44,6 +55,16 @@ class Context:
 
     # ------------------------------------------------------------- helpers
     net = None
+
+    @staticmethod
+    def workspace_bytes(nx: int, ny: int, nz: int, m_max: int = 100) -> int:
+        """Device bytes of a caller workspace for this grid and Krylov basis length m_max."""
+        lib = _lib.load()
+        b = C.c_size_t()
+        rc = lib.lc_workspace_query(int(nx), int(ny), int(nz), int(m_max), C.byref(b))
+        if rc != 0:
+            raise LidKrylovError(rc, "bad workspace query arguments")
+        return int(b.value)
 
     def _check(self, rc, allow_notconv=False):
         if rc == 0 or (allow_notconv and rc == _lib.LC_ENOTCONV):
@@ -182,6 +203,36 @@ class Context:
                                                    int(precision), float(tol), int(max_iter), C.byref(st)),
                          allow_notconv=True)
         return v, p, dict(st.as_dict(), converged=(rc == 0))
+
+    # ---------------------------------------- Stokes-preconditioned vectors
+    def viscous_solve(self, f, dt, out=None):
+        """u = (I/dt - Re^-1 Lap_0)^-1 f (dt = float('inf'): the pure Stokes operator)."""
+        out = self.vel() if out is None else out
+        self._check(self.lib.lc_viscous_solve(self._h, self._ptr(f, self.nvel, "f"), self._ptr(out, self.nvel, "u"),
+                                              float(dt)))
+        return out
+
+    def stokes_step(self, f, dt, out=None, precision=FP64, tol=1e-12, max_iter=8):
+        """u = P (I/dt - Re^-1 Lap_0)^-1 f: the viscous step, then the projection."""
+        out = self.vel() if out is None else out
+        st = Stats()
+        rc = self._check(self.lib.lc_stokes_step(self._h, self._ptr(f, self.nvel, "f"), self._ptr(out, self.nvel, "u"),
+                                                 float(dt), int(precision), float(tol), int(max_iter), C.byref(st)),
+                         allow_notconv=True)
+        return out, dict(st.as_dict(), converged=(rc == 0))
+
+    def stokes_vector(self, v, dt, out=None, precision=FP64, tol=1e-12, max_iter=8):
+        """The Stokes-preconditioned Krylov vector P (I/dt - Re^-1 Lap_0)^-1 P L_U v."""
+        out = self.vel() if out is None else out
+        st = Stats()
+        rc = self._check(self.lib.lc_stokes_vector(self._h, self._ptr(v, self.nvel, "v"),
+                                                   self._ptr(out, self.nvel, "out"), float(dt), int(precision),
+                                                   float(tol), int(max_iter), C.byref(st)), allow_notconv=True)
+        return out, dict(st.as_dict(), converged=(rc == 0))
+
+    def set_stokes_precond(self, dt):
+        """Right-precondition Newton's linear solves by the Stokes step of time step dt (0: off)."""
+        self._check(self.lib.lc_set_stokes_precond(self._h, float(dt)))
 
     # ------------------------------------------------------ Krylov drivers
     def newton_residual(self, out=None):

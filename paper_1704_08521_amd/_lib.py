@@ -49,6 +49,8 @@ _SIGS = {
     "lc_version": (C.c_char_p, []),
     "lc_last_error": (C.c_char_p, [_P]),
     "lc_create": (_I, [C.POINTER(_P), _I, _I, _I, _P]),
+    "lc_create_in": (_I, [C.POINTER(_P), _I, _I, _I, _P, C.c_size_t, _P]),
+    "lc_workspace_query": (_I, [_I, _I, _I, _I, C.POINTER(C.c_size_t)]),
     "lc_destroy": (_I, [_P]),
     "lc_set_stream": (_I, [_P, _P]),
     "lc_vel_size": (C.c_size_t, [_P]),
@@ -90,6 +92,10 @@ _SIGS = {
     "lc_learned_guess": (_I, [_P, _P, _P, C.POINTER(_D)]),
     "lc_plane_project": (_I, [_P, _P, _I, _P, _P]),
     "lc_set_poisson_method": (_I, [_P, _I]),
+    "lc_viscous_solve": (_I, [_P, _P, _P, _D]),
+    "lc_stokes_step": (_I, [_P, _P, _P, _D, _I, _D, _I, C.POINTER(Stats)]),
+    "lc_stokes_vector": (_I, [_P, _P, _P, _D, _I, _D, _I, C.POINTER(Stats)]),
+    "lc_set_stokes_precond": (_I, [_P, _D]),
     "lc_profile_enable": (_I, [_P, _I]),
     "lc_profile_read": (_I, [_P, _I, C.POINTER(_D), C.POINTER(C.c_long)]),
     "lc_profile_name": (C.c_char_p, [_I]),

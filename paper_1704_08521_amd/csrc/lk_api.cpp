@@ -13,6 +13,7 @@
 #include "lk_ctx.h"
 #include "lk_internal.h"
 #include "lk_linalg.h"
+#include "lk_modes.h"
 
 using namespace lk;
 
@@ -46,9 +47,41 @@ hipEvent_t take_event(lc_ctx* c) {
 
 
 
-template <typename T>
-hipError_t dalloc(T** p, size_t n) {
-  return hipMalloc((void**)p, (n ? n : 1) * sizeof(T));
+constexpr size_t kArenaAlign = 256;
+
+size_t arena_next(const lc_ctx* c) { return (c->arena_used + kArenaAlign - 1) / kArenaAlign * kArenaAlign; }
+
+hipError_t ctx_alloc(lc_ctx* c, void** p, size_t bytes) {
+  if (c->dry) {
+    *p = nullptr;
+    c->arena_used = arena_next(c) + bytes;
+    return hipSuccess;
+  }
+  if (!c->arena) return hipMalloc(p, bytes);
+  const size_t at = arena_next(c);
+  if (at + bytes > c->arena_size) return hipErrorOutOfMemory;
+  *p = c->arena + at;
+  c->arena_used = at + bytes;
+  return hipSuccess;
+}
+
+int krylov_ws(lc_ctx* c, int nvec, double** p, long* ld) {
+  *ld = ((long)c->nvel + 63) / 64 * 64;
+  const size_t need = (size_t)nvec * *ld;
+  if (need > c->kws_n) {
+    if (c->arena)
+      return fail(c, LC_ENOMEM, "workspace too small: %d Krylov vectors need %zu bytes, %zu remain", nvec,
+                  need * sizeof(double), c->kws_n * sizeof(double));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (c->kws) (void)hipFree(c->kws);
+    c->kws = nullptr;
+    c->kws_n = 0;
+    if (hipMalloc((void**)&c->kws, need * sizeof(double)) != hipSuccess)
+      return fail(c, LC_ENOMEM, "cannot allocate %d Krylov vectors (%.1f GB)", nvec, need * 8e-9);
+    c->kws_n = need;
+  }
+  *p = c->kws;
+  return LC_OK;
 }
 
 double now_ms() {
@@ -78,9 +111,8 @@ int vnorm_div(lc_ctx* c, const double* v, double* r, double* out) {
 int upload_grid(lc_ctx* c) {
   const int n[3] = {c->nx, c->ny, c->nz};
   // metrics: per axis rd (n), rdd (n+1), th (n+1), d (n)
-  size_t total = 0;
-  for (int a = 0; a < 3; ++a) total += 4 * (size_t)n[a] + 2;
-  if (!c->metric) HIPCHK(c, dalloc(&c->metric, total));
+  const size_t total = metric_doubles(n[0], n[1], n[2]);
+  if (!c->metric) HIPCHK(c, dalloc(c, &c->metric, total));
   std::vector<double> host(total);
   size_t off = 0;
   AxisDev* dst[3] = {&c->g.x, &c->g.y, &c->g.z};
@@ -104,155 +136,34 @@ int upload_grid(lc_ctx* c) {
   HIPCHK(c, hipMemcpyAsync(c->metric, host.data(), total * sizeof(double), hipMemcpyHostToDevice, c->stream));
 
   // tensor-product factorization of each axis (full matrices, plus the parity-sorted
-  // half matrices of mirror-symmetric axes: at most 2.5 n^2 values each in both precisions)
+  // half matrices of mirror-symmetric axes, in both precisions)
   size_t mbytes = 0;
-  for (int a = 0; a < 3; ++a) {
-    const size_t nn = (size_t)n[a] * n[a];
-    const size_t half = 3 * nn;
-    const int he = (n[a] + 1) / 2;
-    mbytes += 2 * n[a] * sizeof(double) + 4 * nn * sizeof(double) + 4 * nn * sizeof(float) +
-              half * (sizeof(double) + sizeof(float)) + 4 * (mf_pack_size(he, 2) * sizeof(double) +
-                                                             mf_pack_size(he, 4) * sizeof(float)) +
-              64 * 16;  // alignment padding (at most 15 bytes for each of an axis' <= 34 arrays)
-  }
-  if (!c->modes_mem) HIPCHK(c, hipMalloc(&c->modes_mem, mbytes));
-  std::vector<char> mhost(mbytes);
-  char* hp = mhost.data();
-  char* dp = (char*)c->modes_mem;
-  bool overflow = false;
+  for (int a = 0; a < 3; ++a) mbytes += mode_bytes(n[a]);
+  if (!c->modes_mem) HIPCHK(c, ctx_alloc(c, &c->modes_mem, mbytes));
+  Stager st(mbytes, c->modes_mem);
   for (int a = 0; a < 3; ++a) {
     const int m = n[a];
-    const size_t nn = (size_t)m * m;
-    std::vector<double> lam, S, Wf;
-    if (!neumann_modes(m, c->ax[a].d.data(), c->ax[a].dd.data(), lam, S, Wf))
-      return fail(c, LC_EINVAL, "tridiagonal eigen-solver did not converge on axis %d", a);
-    c->zero_mode[a] = m - 1;  // ascending; the Neumann null mode is the largest (~0)
-    std::vector<double> F(Wf), Bk(S), FT(nn), BkT(nn);
-    for (int i = 0; i < m; ++i)
-      for (int j = 0; j < m; ++j) {
-        FT[(size_t)j * m + i] = F[(size_t)i * m + j];
-        BkT[(size_t)j * m + i] = Bk[(size_t)i * m + j];
-      }
-    AxisModes& M = c->modes[a];
-    // every array starts 16-byte aligned (the matrix-core kernels read packs 16 bytes a lane)
-    auto align16 = [&]() {
-      const size_t pad = (16 - (size_t)(hp - mhost.data()) % 16) % 16;
-      hp += pad;
-      dp += pad;
-    };
-    auto fits = [&](size_t bytes) {  // never write past the host staging buffer
-      if ((size_t)(hp - mhost.data()) + bytes <= mbytes) return true;
-      overflow = true;
-      return false;
-    };
-    auto put_d = [&](const std::vector<double>& v, double** dptr) {
-      align16();
-      if (!fits(v.size() * sizeof(double))) return;
-      std::memcpy(hp, v.data(), v.size() * sizeof(double));
-      *dptr = (double*)dp;
-      hp += v.size() * sizeof(double);
-      dp += v.size() * sizeof(double);
-    };
-    auto put_f = [&](const std::vector<double>& v, float** dptr) {
-      align16();
-      if (!fits(v.size() * sizeof(float))) return;
-      for (size_t q = 0; q < v.size(); ++q) ((float*)hp)[q] = (float)v[q];
-      *dptr = (float*)dp;
-      hp += v.size() * sizeof(float);
-      dp += v.size() * sizeof(float);
-    };
-    put_d(lam, &M.lam);
-    put_d(F, &M.F);
-    put_d(Bk, &M.Bk);
-    put_d(FT, &M.FT);
-    put_d(BkT, &M.BkT);
-    put_f(F, &M.F32);
-    put_f(Bk, &M.Bk32);
-    put_f(FT, &M.FT32);
-    put_f(BkT, &M.BkT32);
-    // mirror symmetry: widths and centre distances equal under i -> m-1-i
     const AxisHost& AH = c->ax[a];
+    // mirror symmetry: widths and centre distances equal under i -> m-1-i
     bool sym = m >= 2;
     double wmax = 0.0;
     for (int i = 0; i < m; ++i) wmax = std::max(wmax, AH.d[i]);
     for (int i = 0; i < m && sym; ++i) sym = std::fabs(AH.d[i] - AH.d[m - 1 - i]) <= 1e-12 * wmax;
     for (int i = 0; i <= m && sym; ++i) sym = std::fabs(AH.dd[i] - AH.dd[m - i]) <= 1e-12 * wmax;
-    const int he = (m + 1) / 2, ho = m / 2;
-    std::vector<double> lam_e, lam_o, Sh_e, Sh_o;
-    if (sym && (!neumann_half_modes(m, AH.d.data(), AH.dd.data(), false, lam_e, Sh_e) ||
-                !neumann_half_modes(m, AH.d.data(), AH.dd.data(), true, lam_o, Sh_o)))
-      return fail(c, LC_EINVAL, "tridiagonal eigen-solver did not converge on axis %d (half problems)", a);
-    M.sym = sym;
-    M.mf = false;
-    M.he = he;
-    M.ho = ho;
-    if (sym) {
-      // parity-sorted modes: the he even ones (ascending, the null mode last), then the odd ones
-      const double r2 = std::sqrt(0.5);
-      const bool mid = (m % 2) == 1;
-      std::vector<double> lam_s(lam_e), h[8];
-      lam_s.insert(lam_s.end(), lam_o.begin(), lam_o.end());
-      c->zero_mode[a] = he - 1;
-      h[0].assign((size_t)he * he, 0.0);
-      h[1].assign((size_t)ho * ho, 0.0);
-      h[2].assign((size_t)he * he, 0.0);
-      h[3].assign((size_t)he * ho, 0.0);
-      // forward: c_k = sum_p A[k][p] fold(r)_p, fold = r_p + r_{m-1-p} (r_mid alone), r_p - r_{m-1-p}
-      for (int k = 0; k < he; ++k)
-        for (int p = 0; p < he; ++p) {
-          const double wgt = (mid && p == he - 1) ? 1.0 : r2;
-          h[0][(size_t)k * he + p] = Sh_e[(size_t)p * he + k] * AH.d[p] * wgt;
-          h[2][(size_t)p * he + k] = Sh_e[(size_t)p * he + k] * wgt;  // backward: phi_p from even modes
-        }
-      for (int k = 0; k < ho; ++k)
-        for (int p = 0; p < ho; ++p) {
-          h[1][(size_t)k * ho + p] = Sh_o[(size_t)p * ho + k] * AH.d[p] * r2;
-          h[3][(size_t)p * ho + k] = Sh_o[(size_t)p * ho + k] * r2;  // rows p < ho; the middle row stays 0
-        }
-      h[4].resize((size_t)he * he);
-      h[5].resize((size_t)ho * ho);
-      h[6].resize((size_t)he * he);
-      h[7].resize((size_t)ho * he);
-      for (int r = 0; r < he; ++r)
-        for (int i = 0; i < he; ++i) {
-          h[4][(size_t)i * he + r] = h[0][(size_t)r * he + i];
-          h[6][(size_t)r * he + i] = h[2][(size_t)i * he + r];
-        }
-      for (int r = 0; r < ho; ++r)
-        for (int i = 0; i < ho; ++i) h[5][(size_t)i * ho + r] = h[1][(size_t)r * ho + i];
-      for (int i = 0; i < he; ++i)
-        for (int r = 0; r < ho; ++r) h[7][(size_t)r * he + i] = h[3][(size_t)i * ho + r];
-      put_d(lam_s, &M.lam_s);
-      for (int q = 0; q < 8; ++q) put_d(h[q], &M.h64[q]);
-      for (int q = 0; q < 8; ++q) put_f(h[q], &M.h32[q]);
-      // fragment packs for the matrix-core transforms: fragment (kq, t, l) =
-      // Mat[o = 16 t + l % 16][k = 4 kq + l / 16], zero outside the matrix, laid out by
-      // mf_pack_index (two FP64 / four FP32 fragments per 16-byte lane load)
-      M.mf = he <= kMfMaxHalf;
-      if (M.mf) {
-        const int RT = (he + 15) / 16, KQ = mf_steps(he);
-        const int rows[4] = {he, ho, he, he}, cols[4] = {he, ho, he, ho};
-        for (int q = 0; q < 4; ++q) {
-          std::vector<double> P2(mf_pack_size(he, 2), 0.0), P4(mf_pack_size(he, 4), 0.0);
-          for (int kq = 0; kq < KQ; ++kq)
-            for (int t = 0; t < RT; ++t)
-              for (int l = 0; l < 64; ++l) {
-                const int o = 16 * t + l % 16, k = 4 * kq + l / 16;
-                if (o < rows[q] && k < cols[q]) {
-                  const double v = h[q][(size_t)o * cols[q] + k];
-                  P2[mf_pack_index(kq, t, l, RT, 2)] = v;
-                  P4[mf_pack_index(kq, t, l, RT, 4)] = v;
-                }
-              }
-          put_d(P2, &M.p64[q]);
-          put_f(P4, &M.p32[q]);
-        }
-      }
-    }
+    c->axis_sym[a] = sym;
+    std::vector<double> kd, ko;
+    neumann_operator(m, AH.dd.data(), kd, ko);
+    ModeHost H;
+    if (!compute_modes(m, kd, ko, AH.d, sym, H))
+      return fail(c, LC_EINVAL, "tridiagonal eigen-solver did not converge on axis %d", a);
+    place_modes(H, c->modes[a], st);
+    // ascending; the Neumann null mode is the largest (~0), last of the even modes when folded
+    c->zero_mode[a] = sym ? (m + 1) / 2 - 1 : m - 1;
   }
-  if (overflow) return fail(c, LC_ENOMEM, "mode storage sized too small (internal)");
-  HIPCHK(c, hipMemcpyAsync(c->modes_mem, mhost.data(), mbytes, hipMemcpyHostToDevice, c->stream));
+  if (st.overflow) return fail(c, LC_ENOMEM, "mode storage sized too small (internal)");
+  HIPCHK(c, hipMemcpyAsync(c->modes_mem, st.host.data(), st.used, hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->stokes_ready = false;  // the viscous-step factors belong to the previous grid
   c->grid_ready = true;
   return LC_OK;
 }
@@ -427,35 +338,94 @@ const char* lc_last_error(const lc_ctx* c) { return c ? c->err.c_str() : g_creat
 size_t lc_vel_size(const lc_ctx* c) { return c ? c->nvel : 0; }
 size_t lc_cell_size(const lc_ctx* c) { return c ? c->ncell : 0; }
 
-int lc_create(lc_ctx** out, int nx, int ny, int nz, void* hip_stream) {
+}  // extern "C"
+
+namespace lk {
+
+size_t metric_doubles(int nx, int ny, int nz) { return 4 * ((size_t)nx + ny + nz) + 6; }
+
+size_t viscous_bytes(int nx, int ny, int nz) {
+  size_t b = 0;
+  for (int n : {nx, ny, nz}) b += mode_bytes(n) + mode_bytes(n + 1);
+  return b;
+}
+
+size_t component_max(int nx, int ny, int nz) {
+  return std::max({(size_t)(nx + 1) * ny * nz, (size_t)nx * (ny + 1) * nz, (size_t)nx * ny * (nz + 1)});
+}
+
+// Krylov vectors the drivers use with basis or restart length m: Arnoldi 2 (m + 1), Newton
+// max(m + 1, 8) + 4 (GMRES basis, BiCGstab(2) vectors, right side, correction, spares).
+int krylov_vectors(int m) { return std::max(2 * (m + 1), std::max(m + 1, 8) + 4); }
+
+namespace {
+
+void init_dims(lc_ctx* c, int nx, int ny, int nz) {
+  c->nx = nx;
+  c->ny = ny;
+  c->nz = nz;
+  c->nvel = vel_layout(nx, ny, nz).total();
+  c->ncell = (size_t)nx * ny * nz;
+  c->max_parts = (int)((c->ncell + kReduceBlock - 1) / kReduceBlock) + kGsBlocks * kGsChunk;
+  // the divergence kernel: 64 x 4 cells x 4 planes per block
+  const size_t nd = (size_t)((nx + 63) / 64) * ((ny + 3) / 4) * ((nz + 3) / 4);
+  if (nd > (size_t)c->max_parts) c->max_parts = (int)nd;
+}
+
+// The context's device buffers, in a fixed order.  With a caller workspace (or a dry run)
+// the buffers that are otherwise allocated on first use -- grid metrics and factors, the
+// viscous-step factors, the critical-Re steady states -- are carved here as well, and the
+// Krylov vectors get the remainder.
+bool carve_all(lc_ctx* c) {
+  bool ok = dalloc(c, &c->U, c->nvel) == hipSuccess && dalloc(c, &c->w, c->nvel) == hipSuccess &&
+            dalloc(c, &c->r, c->ncell) == hipSuccess && dalloc(c, &c->phi, c->ncell) == hipSuccess &&
+            dalloc(c, &c->t1, c->ncell) == hipSuccess && dalloc(c, &c->t2, c->ncell) == hipSuccess &&
+            dalloc(c, &c->r32, c->ncell) == hipSuccess && dalloc(c, &c->t1_32, c->ncell) == hipSuccess &&
+            dalloc(c, &c->t2_32, c->ncell) == hipSuccess && dalloc(c, &c->partials, c->max_parts) == hipSuccess &&
+            dalloc(c, &c->dsum, 1) == hipSuccess && dalloc(c, &c->dsmall, kSmall) == hipSuccess;
+  if (!ok || !(c->arena || c->dry)) return ok;
+  const int nx = c->nx, ny = c->ny, nz = c->nz;
+  size_t mbytes = 0;
+  for (int n : {nx, ny, nz}) mbytes += mode_bytes(n);
+  return dalloc(c, &c->metric, metric_doubles(nx, ny, nz)) == hipSuccess &&
+         ctx_alloc(c, &c->modes_mem, mbytes) == hipSuccess &&
+         ctx_alloc(c, &c->stokes_mem, viscous_bytes(nx, ny, nz)) == hipSuccess &&
+         dalloc(c, &c->vscale, 2 * ((size_t)nx + ny + nz) + 3) == hipSuccess &&
+         dalloc(c, &c->hs, component_max(nx, ny, nz)) == hipSuccess &&
+         dalloc(c, &c->ucr, 3 * c->nvel) == hipSuccess;
+}
+
+int create(lc_ctx** out, int nx, int ny, int nz, void* ws, size_t ws_bytes, void* hip_stream) {
   if (!out) return fail(nullptr, LC_EINVAL, "null output pointer");
   *out = nullptr;
   if (nx < 2 || ny < 2 || nz < 2 || nx > 4096 || ny > 4096 || nz > 4096)
     return fail(nullptr, LC_EINVAL, "grid size %dx%dx%d outside [2, 4096]", nx, ny, nz);
   lc_ctx* c = new lc_ctx();
-  c->nx = nx;
-  c->ny = ny;
-  c->nz = nz;
+  init_dims(c, nx, ny, nz);
   c->stream = (hipStream_t)hip_stream;
-  c->nvel = vel_layout(nx, ny, nz).total();
-  c->ncell = (size_t)nx * ny * nz;
-  c->max_parts = (int)((c->ncell + kReduceBlock - 1) / kReduceBlock) + kGsBlocks * kGsChunk;
-  {  // the divergence kernel: 64 x 4 cells x 4 planes per block
-    const size_t nd = (size_t)((nx + 63) / 64) * ((ny + 3) / 4) * ((nz + 3) / 4);
-    if (nd > (size_t)c->max_parts) c->max_parts = (int)nd;
+  c->arena = (char*)ws;
+  c->arena_size = ws ? ws_bytes : 0;
+  bool ok = carve_all(c);
+  if (ok && c->arena) {  // the Krylov vectors: the rest of the workspace
+    const size_t at = (c->arena_used + 255) / 256 * 256;
+    c->kws = (double*)(c->arena + std::min(at, c->arena_size));
+    c->kws_n = at < c->arena_size ? (c->arena_size - at) / sizeof(double) : 0;
   }
-  bool ok = dalloc(&c->U, c->nvel) == hipSuccess && dalloc(&c->w, c->nvel) == hipSuccess &&
-            dalloc(&c->r, c->ncell) == hipSuccess && dalloc(&c->phi, c->ncell) == hipSuccess &&
-            dalloc(&c->t1, c->ncell) == hipSuccess && dalloc(&c->t2, c->ncell) == hipSuccess &&
-            dalloc(&c->r32, c->ncell) == hipSuccess && dalloc(&c->t1_32, c->ncell) == hipSuccess &&
-            dalloc(&c->t2_32, c->ncell) == hipSuccess && dalloc(&c->partials, c->max_parts) == hipSuccess &&
-            dalloc(&c->dsum, 1) == hipSuccess && dalloc(&c->dsmall, kSmall) == hipSuccess &&
-            dalloc(&c->pk, c->ncell) == hipSuccess &&
-            hipHostMalloc((void**)&c->hsmall, kSmall * sizeof(double), hipHostMallocDefault) == hipSuccess &&
-            hipHostMalloc((void**)&c->hsum, sizeof(double), hipHostMallocDefault) == hipSuccess;
   if (!ok) {
     lc_destroy(c);
+    if (ws) {
+      size_t need = 0;
+      lc_workspace_query(nx, ny, nz, 0, &need);
+      return fail(nullptr, LC_ENOMEM, "workspace of %zu bytes too small for a %dx%dx%d context (at least %zu)",
+                  ws_bytes, nx, ny, nz, need);
+    }
     return fail(nullptr, LC_ENOMEM, "device allocation failed for %dx%dx%d", nx, ny, nz);
+  }
+  ok = hipHostMalloc((void**)&c->hsmall, kSmall * sizeof(double), hipHostMallocDefault) == hipSuccess &&
+       hipHostMalloc((void**)&c->hsum, sizeof(double), hipHostMallocDefault) == hipSuccess;
+  if (!ok) {
+    lc_destroy(c);
+    return fail(nullptr, LC_ENOMEM, "pinned host allocation failed");
   }
   if (hipMemsetAsync(c->U, 0, c->nvel * sizeof(double), c->stream) != hipSuccess) {
     lc_destroy(c);
@@ -471,14 +441,43 @@ int lc_create(lc_ctx** out, int nx, int ny, int nz, void* hip_stream) {
   return LC_OK;
 }
 
+}  // namespace
+}  // namespace lk
+
+extern "C" {
+
+int lc_workspace_query(int nx, int ny, int nz, int m_max, size_t* bytes) {
+  if (!bytes || nx < 2 || ny < 2 || nz < 2 || nx > 4096 || ny > 4096 || nz > 4096 || m_max < 0 || m_max > 400)
+    return LC_EINVAL;
+  lc_ctx c;
+  init_dims(&c, nx, ny, nz);
+  c.dry = true;
+  carve_all(&c);
+  const size_t at = (c.arena_used + 255) / 256 * 256;
+  const size_t ld = (c.nvel + 63) / 64 * 64;
+  *bytes = at + (size_t)krylov_vectors(m_max) * ld * sizeof(double);
+  return LC_OK;
+}
+
+int lc_create(lc_ctx** out, int nx, int ny, int nz, void* hip_stream) {
+  return create(out, nx, ny, nz, nullptr, 0, hip_stream);
+}
+
+int lc_create_in(lc_ctx** out, int nx, int ny, int nz, void* workspace, size_t bytes, void* hip_stream) {
+  if (!workspace || (uintptr_t)workspace % 256) return fail(nullptr, LC_EINVAL, "workspace must be 256-byte aligned");
+  return create(out, nx, ny, nz, workspace, bytes, hip_stream);
+}
+
 int lc_destroy(lc_ctx* c) {
   if (!c) return LC_OK;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   else (void)hipDeviceSynchronize();
-  void* ptrs[] = {c->U, c->w, c->r, c->phi, c->t1, c->t2, c->r32, c->t1_32, c->t2_32, c->partials,
-                  c->dsum, c->metric, c->modes_mem, c->dsmall, c->pk, c->kws, c->ucr};
-  for (void* p : ptrs)
-    if (p) (void)hipFree(p);
+  if (!c->arena) {  // carved buffers belong to the caller's workspace
+    void* ptrs[] = {c->U, c->w, c->r, c->phi, c->t1, c->t2, c->r32, c->t1_32, c->t2_32, c->partials,
+                    c->dsum, c->metric, c->modes_mem, c->dsmall, c->kws, c->ucr, c->stokes_mem, c->vscale, c->hs};
+    for (void* p : ptrs)
+      if (p) (void)hipFree(p);
+  }
   if (c->hsum) (void)hipHostFree(c->hsum);
   if (c->hsmall) (void)hipHostFree(c->hsmall);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
@@ -632,7 +631,8 @@ int lc_project(lc_ctx* c, const double* w, double* v, double* p, int precision, 
   const double t0 = now_ms();
   int rc = check_ready(c);
   if (rc) return rc;
-  if (!aligned(w) || !aligned(v) || !aligned(p) || v == w) return fail(c, LC_EINVAL, "bad pointers");
+  if (!aligned(w) || !aligned(v) || (p && !aligned(p)) || v == w || p == w || p == v)
+    return fail(c, LC_EINVAL, "bad pointers");
   if (precision != LC_FP64 && precision != LC_MIXED && precision != LC_LEARNED)
     return fail(c, LC_EINVAL, "unknown precision");
   if (precision == LC_LEARNED && !c->net) return fail(c, LC_ESTATE, "no network attached for the learned form");

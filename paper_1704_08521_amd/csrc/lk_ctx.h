@@ -88,15 +88,32 @@ struct lc_ctx {
     int kid;
     hipEvent_t a, b;
   };
-  // Krylov drivers: basis workspace (grown on demand), small device/host scalars,
-  // the discarded pressure of Krylov maps
+  // Krylov drivers: basis workspace (grown on demand), small device/host scalars
   double* kws = nullptr;
   size_t kws_n = 0;
   double* dsmall = nullptr;  // kSmall doubles
   double* hsmall = nullptr;  // kSmall doubles, pinned
-  double* pk = nullptr;      // cell
   double* ucr = nullptr;     // critical-Re driver: two stored steady states + a residual
   lc_net* net = nullptr;     // learned guess (not owned)
+  // Stokes-preconditioned vectors: the viscous step (I/dt - Re^-1 Lap_0)^-1 by the tensor
+  // product of the Dirichlet factors of each axis (cell-centred: n points, faces: n + 1),
+  // built on first use for the current grid
+  bool axis_sym[3] = {false, false, false};
+  bool stokes_ready = false;
+  void* stokes_mem = nullptr;
+  AxisModes vcell[3], vface[3];
+  std::vector<double> vlam_cell[3], vlam_face[3];  // eigenvalues in kernel order (parity-sorted if folded)
+  double* vscale = nullptr;   // device: scaled eigenvalues (cell x, face x, cell y, face y, cell z, face z)
+  size_t vscale_off[6] = {};
+  double vscale_re = 0.0, vscale_dt = -1.0;  // (Re, dt) vscale was built for
+  double* hs = nullptr;       // component-sized transform temporary
+  double stokes_dt = 0.0;     // Newton preconditioning by the viscous step (0: off)
+  // Caller-provided workspace (lc_create_in): every device buffer of the context is carved
+  // from it in a fixed order at creation, the Krylov vectors take what remains, and the
+  // library allocates no device memory.  `dry` sizes the carve without memory (the query).
+  char* arena = nullptr;
+  size_t arena_size = 0, arena_used = 0;
+  bool dry = false;
   bool prof = false;
   std::vector<Rec> recs;
   std::vector<hipEvent_t> ev_pool;
@@ -107,6 +124,24 @@ struct lc_ctx {
 namespace lk {
 
 constexpr int kSmall = 16384;
+
+// Device memory of a context: carved from the caller's workspace when there is one (256-byte
+// aligned; hipErrorOutOfMemory when it is exhausted), else hipMalloc'ed.  Freed by
+// lc_destroy only in the second case.
+hipError_t ctx_alloc(lc_ctx* c, void** p, size_t bytes);
+template <typename T>
+hipError_t dalloc(lc_ctx* c, T** p, size_t n) {
+  return ctx_alloc(c, (void**)p, (n ? n : 1) * sizeof(T));
+}
+// Sizes of the lazily allocated buffers (doubles unless bytes): grid metrics, viscous-step
+// factors, the largest velocity component; Krylov vectors of drivers with basis length m.
+size_t metric_doubles(int nx, int ny, int nz);
+size_t viscous_bytes(int nx, int ny, int nz);
+size_t component_max(int nx, int ny, int nz);
+int krylov_vectors(int m);
+// Krylov vectors: `nvec` velocities ld = lc_vel_size rounded up to 64 apart (grown on demand,
+// or the remainder of the caller's workspace: LC_ENOMEM when it holds fewer).
+int krylov_ws(lc_ctx* c, int nvec, double** p, long* ld);
 
 int fail(lc_ctx* c, int code, const char* fmt, ...);
 hipEvent_t take_event(lc_ctx* c);
@@ -123,6 +158,10 @@ int poisson(lc_ctx* c, const double* r, double* phi, int precision);
 // Euclidean dot product / max |x| of velocity vectors, host results
 int vdot(lc_ctx* c, const double* a, const double* b, double* out);
 int vmaxabs(lc_ctx* c, const double* a, double* out);
+// viscous step u = (I/dt - Re^-1 Lap_0)^-1 f (velocities, distinct; dt may be infinite),
+// and the Stokes step u = P (viscous step of f) (lk_stokes.cpp; uses c->w)
+int viscous_solve(lc_ctx* c, const double* f, double* u, double dt);
+int stokes_step(lc_ctx* c, const double* f, double* u, double dt, int precision, double tol, int max_iter);
 // learned start of the SIMPLE loop (see lk_nn_host.cpp); requires c->net
 int learned_start(lc_ctx* c, const double* w, double* v, double* p, bool* used, double* eps_fit);
 

@@ -27,41 +27,35 @@ struct Basis {
   double* at(int i) const { return p + (size_t)i * ld; }
 };
 
-// Device workspace of `nvec` velocity vectors, ld apart (grown on demand).
-int ensure_ws(lc_ctx* c, int nvec, Basis* B) {
-  const long ld = ((long)c->nvel + 63) / 64 * 64;
-  const size_t need = (size_t)nvec * ld;
-  if (need > c->kws_n) {
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    if (c->kws) (void)hipFree(c->kws);
-    c->kws = nullptr;
-    c->kws_n = 0;
-    if (hipMalloc((void**)&c->kws, need * sizeof(double)) != hipSuccess)
-      return fail(c, LC_ENOMEM, "cannot allocate %d Krylov vectors (%.1f GB)", nvec, need * 8e-9);
-    c->kws_n = need;
-  }
-  B->p = c->kws;
-  B->ld = ld;
-  return LC_OK;
-}
+// Device workspace of `nvec` velocity vectors, ld apart.
+int ensure_ws(lc_ctx* c, int nvec, Basis* B) { return krylov_ws(c, nvec, &B->p, &B->ld); }
 
 struct KMap {
   int precision;
   double ptol;
   int pmax;
   long count = 0;
+  double sdt = 0.0;      // > 0: right preconditioning by the viscous step with this time step
+  double* z = nullptr;   // its output (velocity), when sdt > 0
 };
 
-// out = P L_U in (one Krylov vector); a projection that misses its tolerance is
-// an error here (the Krylov drivers need the divergence-free subspace).
 bool verbose() {  // read on every call: callers may switch the trace on around one driver call
   const char* e = std::getenv("LK_VERBOSE");
   return e && e[0] && e[0] != '0';
 }
 
+// out = P L_U in (one Krylov vector), or with right preconditioning
+// out = P L_U P (I/dt - Re^-1 Lap_0)^-1 in; a projection that misses its tolerance is an
+// error here (the Krylov drivers need the divergence-free subspace).
 int kmap(lc_ctx* c, KMap& K, const double* in, double* out) {
   lc_stats st;
-  int rc = lc_krylov_vector(c, in, out, c->pk, K.precision, K.ptol, K.pmax, &st);
+  if (K.sdt > 0.0) {
+    int rc = stokes_step(c, in, K.z, K.sdt, K.precision, K.ptol, K.pmax);
+    if (rc == LC_ENOTCONV) return fail(c, LC_ENOTCONV, "preconditioner projection missed its tolerance");
+    if (rc) return rc;
+    in = K.z;
+  }
+  int rc = lc_krylov_vector(c, in, out, nullptr, K.precision, K.ptol, K.pmax, &st);
   K.count++;
   if (rc == LC_ENOTCONV) return fail(c, LC_ENOTCONV, "projection missed its tolerance (rho = %.3e)", st.rho);
   if (rc) {
@@ -94,7 +88,7 @@ double vnorm(double s) { return std::sqrt(std::max(s, 0.0)); }
 // of P L_U, which lies outside the divergence-free space.
 int vproject(lc_ctx* c, double* x, double* tmp) {
   lc_stats st;
-  const int rc = lc_project(c, x, tmp, c->pk, LC_FP64, 1e-13, 4, &st);
+  const int rc = lc_project(c, x, tmp, nullptr, LC_FP64, 1e-13, 4, &st);
   if (rc < 0) return rc;
   return vcopy(c, tmp, x);
 }
@@ -175,7 +169,7 @@ extern "C" int lc_arnoldi_leading(lc_ctx* c, int k, int m, double tol, int max_r
   if ((rc = vdot(c, W.at(0), W.at(0), &wn))) return rc;
   dref /= std::max(vnorm(wn), 1e-300);
   lc_stats st;
-  rc = lc_project(c, W.at(0), V.at(0), c->pk, LC_FP64, 1e-13, 4, &st);
+  rc = lc_project(c, W.at(0), V.at(0), nullptr, LC_FP64, 1e-13, 4, &st);
   if (rc < 0) return rc;
   double nrm = 0.0;
   if ((rc = vdot(c, V.at(0), V.at(0), &nrm))) return rc;
@@ -427,11 +421,14 @@ int bicgstab2(lc_ctx* c, KMap& K, const double* b, double* x, const Basis& S, do
     if ((rc = vdot(c, r0, r0, &rn))) return rc;
     rn = vnorm(rn);
     if (verbose()) std::fprintf(stderr, "[lk bicgstab2] |res| = %.3e (rel %.3e)\n", rn, rn / bnorm);
+    // The residual of BiCGstab(2) is not monotone: on these convection-dominated systems it
+    // rises by 1e2-1e3 for hundreds of iterations before falling (measured at 100^3 near
+    // Re_cr), so only a non-finite residual ends the iteration; the best iterate is kept.
     if (std::isfinite(rn) && rn < best) {
       best = rn;
       if ((rc = vcopy(c, x, xbest))) return rc;
-    } else if (!std::isfinite(rn) || rn > 1e3 * best) {
-      break;  // divergence: fall back to the best iterate
+    } else if (!std::isfinite(rn)) {
+      break;
     }
   }
   if ((rc = vcopy(c, xbest, x))) return rc;
@@ -448,7 +445,7 @@ extern "C" int lc_newton_residual(lc_ctx* c, double* F, double* res_inf) {
   KLAUNCH(c, LC_K_RESIDUAL, launch_momentum(c->g, c->U, c->U, c->w, 1.0 / c->re, 0.5, true, std::cos(c->alpha),
                                             std::sin(c->alpha), c->stream));
   lc_stats st;
-  rc = lc_project(c, c->w, F, c->pk, LC_FP64, 1e-13, 4, &st);
+  rc = lc_project(c, c->w, F, nullptr, LC_FP64, 1e-13, 4, &st);
   if (rc < 0) return rc;
   // R(U) carries an O(1) pressure gradient, so the first projection leaves a
   // divergent residue of ~1e-13 of that size -- as large as F itself near
@@ -466,9 +463,9 @@ extern "C" int lc_newton_step(lc_ctx* c, double lin_tol, int gmres_m, long max_v
     return fail(c, LC_EINVAL, "bad Newton arguments");
   Basis B;
   const int nbasis = std::max(gmres_m + 1, 8);
-  if ((rc = ensure_ws(c, nbasis + 3, &B))) return rc;
+  if ((rc = ensure_ws(c, nbasis + 4, &B))) return rc;
   double* F = B.at(nbasis);      // right side P R(U)
-  double* x = B.at(nbasis + 1);  // the correction
+  double* x = B.at(nbasis + 1);  // the correction (preconditioned: its preimage y, x = M^-1 y)
   double* t = B.at(nbasis + 2);  // spare
   // steps 2-3 of Section 3: residual, then the Jacobian system on the divergence-free space
   double rinf = 0.0;
@@ -476,6 +473,8 @@ extern "C" int lc_newton_step(lc_ctx* c, double lin_tol, int gmres_m, long max_v
   if (res_inf) *res_inf = rinf;
   if (used_bicgstab) *used_bicgstab = 0;
   KMap K{precision, proj_tol, 8};
+  K.sdt = c->stokes_dt;
+  K.z = B.at(nbasis + 3);
   HIPCHK(c, hipMemsetAsync(x, 0, c->nvel * sizeof(double), c->stream));
   double bnorm = 0.0;
   if ((rc = vdot(c, F, F, &bnorm))) return rc;
@@ -562,6 +561,11 @@ extern "C" int lc_newton_step(lc_ctx* c, double lin_tol, int gmres_m, long max_v
     if ((rc = bicgstab2(c, K, F, x, S, bnorm, lin_tol, max_vectors, &fr))) return rc;
     solved = fr <= lin_tol * bnorm;
   }
+  // right preconditioning: the Krylov solve was for y with (P L_U M^-1) y = F; x = M^-1 y
+  if (K.sdt > 0.0) {
+    if ((rc = stokes_step(c, x, t, K.sdt, LC_FP64, 1e-13, 4)) < 0) return rc;
+    if ((rc = vcopy(c, t, x))) return rc;
+  }
   // step 4: U <- U - x, with x kept in the divergence-free space
   if ((rc = vproject(c, x, t))) return rc;
   if ((rc = vaxpy(c, -1.0, x, c->U))) return rc;
@@ -584,7 +588,7 @@ extern "C" int lc_critical_re(lc_ctx* c, double re0, double re1, const lc_critic
   if (o->max_evals < 2 || o->newton_steps < 0 || !(o->re_tol > 0.0) || !(o->newton_tol > 0.0))
     return fail(c, LC_EINVAL, "bad critical-Re options");
   *n_evals = 0;
-  if (!c->ucr && hipMalloc((void**)&c->ucr, 3 * c->nvel * sizeof(double)) != hipSuccess)
+  if (!c->ucr && dalloc(c, &c->ucr, 3 * c->nvel) != hipSuccess)
     return fail(c, LC_ENOMEM, "cannot allocate the stored steady states");
   double* Us[2] = {c->ucr, c->ucr + c->nvel};  // the last two steady states, oldest first
   double* Fr = c->ucr + 2 * c->nvel;            // projected residual (scratch)

@@ -253,41 +253,37 @@ void shifted_qr_step(int m, std::vector<double>& H, std::vector<double>& Q, doub
   Q.swap(Qn);
 }
 
-bool neumann_modes(int n, const double* d, const double* dd, std::vector<double>& lam, std::vector<double>& S,
-                   std::vector<double>& Wf) {
-  // K: couplings 1/dd on interior faces; M = diag(d).  T = M^-1/2 K M^-1/2.
+bool tridiag_modes(int n, const double* kd, const double* ko, const double* m, std::vector<double>& lam,
+                   std::vector<double>& S, std::vector<double>& Wf) {
+  // T = M^-1/2 K M^-1/2 is symmetric tridiagonal; its eigenvectors q give s = M^-1/2 q.
   std::vector<double> a(n, 0.0), b(std::max(n - 1, 1), 0.0);
-  for (int f = 1; f < n; ++f) {
-    const double c = 1.0 / dd[f];
-    a[f - 1] -= c;
-    a[f] -= c;
-    b[f - 1] = c / std::sqrt(d[f - 1] * d[f]);
-  }
-  for (int i = 0; i < n; ++i) a[i] /= d[i];
+  for (int i = 0; i < n; ++i) a[i] = kd[i] / m[i];
+  for (int i = 0; i + 1 < n; ++i) b[i] = ko[i] / std::sqrt(m[i] * m[i + 1]);
   std::vector<double> Q;
   if (!sym_tridiag_eig(n, a, b, lam, Q)) return false;
   S.resize((size_t)n * n);
   Wf.resize((size_t)n * n);
   for (int i = 0; i < n; ++i) {
-    const double sq = std::sqrt(d[i]);
-    for (int m = 0; m < n; ++m) {
-      const double q = Q[(size_t)i * n + m];
-      S[(size_t)i * n + m] = q / sq;   // S = M^-1/2 Q, S^T M S = I
-      Wf[(size_t)m * n + i] = q * sq;  // S^T M
+    const double sq = std::sqrt(m[i]);
+    for (int k = 0; k < n; ++k) {
+      const double q = Q[(size_t)i * n + k];
+      S[(size_t)i * n + k] = q / sq;   // S = M^-1/2 Q, S^T M S = I
+      Wf[(size_t)k * n + i] = q * sq;  // S^T M
     }
   }
   return true;
 }
 
-// Modes of a mirror-symmetric axis (d[i] = d[n-1-i], dd[f] = dd[n-f]) restricted to the
-// even or odd subspace.  Basis: e_p = (delta_p + delta_{n-1-p}) / sqrt2 (p < n/2) plus
-// delta_mid for odd n (even), o_p = (delta_p - delta_{n-1-p}) / sqrt2 (odd).  The
-// projected K and M are tridiagonal and diagonal, so the half problem is solved like
-// the full one; its eigenvectors are exactly even / odd, which separates the nearly
-// degenerate mirror pairs that wall-refined grids produce.  Outputs: lam (h ascending),
-// Sh (h x h, row-major [p][k]): the k-th mode in the basis, Sh^T Mh Sh = I.
-bool neumann_half_modes(int n, const double* d, const double* dd, bool odd, std::vector<double>& lam,
-                        std::vector<double>& Sh) {
+// The operator restricted to the even or odd subspace of a mirror-symmetric problem
+// (kd[i] = kd[n-1-i], ko[i] = ko[n-2-i], m[i] = m[n-1-i]).  Basis: e_p = (delta_p +
+// delta_{n-1-p}) / sqrt2 (p < n/2) plus delta_mid for odd n (even), o_p = (delta_p -
+// delta_{n-1-p}) / sqrt2 (odd).  The projected K and M are tridiagonal and diagonal, so
+// the half problem is solved like the full one; its eigenvectors are exactly even / odd,
+// which separates the nearly degenerate mirror pairs that wall-refined grids produce.
+// Outputs: lam (h ascending), Sh (h x h, row-major [p][k]): the k-th mode in the basis,
+// Sh^T Mh Sh = I.
+bool tridiag_half_modes(int n, const double* kd, const double* ko, const double* m, bool odd,
+                        std::vector<double>& lam, std::vector<double>& Sh) {
   const int he = (n + 1) / 2, ho = n / 2;
   const int h = odd ? ho : he;
   if (h == 0) {
@@ -296,16 +292,10 @@ bool neumann_half_modes(int n, const double* d, const double* dd, bool odd, std:
     return true;
   }
   const double r2 = std::sqrt(0.5);
-  // full operator entries: K[i][i] = -(c_i + c_{i+1}), K[i][i+1] = c_{i+1}, c_f = 1/dd[f], walls 0
   auto K = [&](int i, int j) -> double {
-    if (j == i) {
-      double v = 0.0;
-      if (i > 0) v -= 1.0 / dd[i];
-      if (i < n - 1) v -= 1.0 / dd[i + 1];
-      return v;
-    }
-    if (j == i + 1) return 1.0 / dd[i + 1];
-    if (j == i - 1) return 1.0 / dd[i];
+    if (j == i) return kd[i];
+    if (j == i + 1) return ko[i];
+    if (j == i - 1) return ko[j];
     return 0.0;
   };
   // basis column p: up to two (index, weight) entries
@@ -330,18 +320,67 @@ bool neumann_half_modes(int n, const double* d, const double* dd, bool odd, std:
       for (int b = 0; b < nq; ++b) v += wp[a] * wq[b] * K(ip[a], iq[b]);
     return v;
   };
-  std::vector<double> m(h), a(h), b(std::max(h - 1, 1), 0.0);
-  for (int p = 0; p < h; ++p) m[p] = d[p];  // e_p^T M e_p = (d_p + d_{n-1-p}) / 2 = d_p
-  for (int p = 0; p < h; ++p) a[p] = proj(p, p) / m[p];
-  for (int p = 0; p + 1 < h; ++p) b[p] = proj(p, p + 1) / std::sqrt(m[p] * m[p + 1]);
+  std::vector<double> mh(h), a(h), b(std::max(h - 1, 1), 0.0);
+  for (int p = 0; p < h; ++p) mh[p] = m[p];  // e_p^T M e_p = (m_p + m_{n-1-p}) / 2 = m_p
+  for (int p = 0; p < h; ++p) a[p] = proj(p, p) / mh[p];
+  for (int p = 0; p + 1 < h; ++p) b[p] = proj(p, p + 1) / std::sqrt(mh[p] * mh[p + 1]);
   std::vector<double> Q;
   if (!sym_tridiag_eig(h, a, b, lam, Q)) return false;
   Sh.resize((size_t)h * h);
   for (int p = 0; p < h; ++p) {
-    const double sq = std::sqrt(m[p]);
+    const double sq = std::sqrt(mh[p]);
     for (int k = 0; k < h; ++k) Sh[(size_t)p * h + k] = Q[(size_t)p * h + k] / sq;
   }
   return true;
+}
+
+void neumann_operator(int n, const double* dd, std::vector<double>& kd, std::vector<double>& ko) {
+  // couplings c_f = 1/dd[f] across the interior faces f = 1..n-1; none through the walls
+  kd.assign(n, 0.0);
+  ko.assign(std::max(n - 1, 1), 0.0);
+  for (int i = 0; i < n; ++i) {
+    double v = 0.0;
+    if (i > 0) v -= 1.0 / dd[i];
+    if (i < n - 1) v -= 1.0 / dd[i + 1];
+    kd[i] = v;
+  }
+  for (int i = 0; i + 1 < n; ++i) ko[i] = 1.0 / dd[i + 1];
+}
+
+void dirichlet_cell_operator(int n, const double* dd, std::vector<double>& kd, std::vector<double>& ko) {
+  // couplings c_f = 1/dd[f] across every face f = 0..n, the two walls (half widths) included
+  kd.assign(n, 0.0);
+  ko.assign(std::max(n - 1, 1), 0.0);
+  for (int i = 0; i < n; ++i) kd[i] = -(1.0 / dd[i] + 1.0 / dd[i + 1]);
+  for (int i = 0; i + 1 < n; ++i) ko[i] = 1.0 / dd[i + 1];
+}
+
+void dirichlet_face_operator(int n, const double* d, const double* dd, std::vector<double>& kd,
+                             std::vector<double>& ko, std::vector<double>& m) {
+  // n + 1 points (faces 0..n): interior face i couples to i -+ 1 through cells i-1, i
+  // (1/d), mass dd[i]; the wall faces are decoupled points with K = -1, M = 1
+  kd.assign(n + 1, -1.0);
+  ko.assign(n, 0.0);
+  m.assign(n + 1, 1.0);
+  for (int i = 1; i < n; ++i) {
+    kd[i] = -(1.0 / d[i - 1] + 1.0 / d[i]);
+    m[i] = dd[i];
+  }
+  for (int i = 1; i + 1 < n; ++i) ko[i] = 1.0 / d[i];
+}
+
+bool neumann_modes(int n, const double* d, const double* dd, std::vector<double>& lam, std::vector<double>& S,
+                   std::vector<double>& Wf) {
+  std::vector<double> kd, ko;
+  neumann_operator(n, dd, kd, ko);
+  return tridiag_modes(n, kd.data(), ko.data(), d, lam, S, Wf);
+}
+
+bool neumann_half_modes(int n, const double* d, const double* dd, bool odd, std::vector<double>& lam,
+                        std::vector<double>& Sh) {
+  std::vector<double> kd, ko;
+  neumann_operator(n, dd, kd, ko);
+  return tridiag_half_modes(n, kd.data(), ko.data(), d, odd, lam, Sh);
 }
 
 }  // namespace lk

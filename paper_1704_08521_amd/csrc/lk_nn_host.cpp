@@ -443,19 +443,16 @@ int lc_net_train(lc_ctx* c, lc_net* n, int steps, double lr, uint64_t seed, doub
   const int D = pad4(c->nz), H = pad4(c->ny), W = pad4(c->nx);
   const long P = (long)D * H * W;
   if ((rc = ensure(n, P, true))) return net_to_ctx(c, n, rc);
-  double *rs = nullptr, *v = nullptr, *pd = nullptr;
-  if (hipMalloc(&rs, c->nvel * sizeof(double)) != hipSuccess || hipMalloc(&v, c->nvel * sizeof(double)) != hipSuccess ||
-      hipMalloc(&pd, c->ncell * sizeof(double)) != hipSuccess) {
-    if (rs) (void)hipFree(rs);
-    if (v) (void)hipFree(v);
-    return fail(c, LC_ENOMEM, "cannot allocate training vectors");
-  }
+  double* rs = nullptr;  // two velocities of the Krylov workspace: the random field and its projection
+  long ld = 0;
+  if ((rc = krylov_ws(c, 2, &rs, &ld))) return rc;
+  double* v = rs + ld;
   auto body = [&]() -> int {
     for (int s = 0; s < steps; ++s) {
       // a pair of the method: v = P(r_s), w = L_U v, phi = first SIMPLE correction of w
       HIPCHK(c, launch_uniform(rs, c->nvel, seed * 1000003ull + (uint64_t)s, c->stream));
       HIPCHK(c, launch_zero_walls(rs, c->nx, c->ny, c->nz, c->stream));
-      int r2 = lc_project(c, rs, v, pd, LC_FP64, 1e-10, 3, nullptr);
+      int r2 = lc_project(c, rs, v, nullptr, LC_FP64, 1e-10, 3, nullptr);
       if (r2 < 0) return r2;
       KLAUNCH(c, LC_K_MOMENTUM, launch_momentum(c->g, c->U, v, c->w, 1.0 / c->re, 1.0, false, 0, 0, c->stream));
       double n0 = 0.0;
@@ -483,9 +480,6 @@ int lc_net_train(lc_ctx* c, lc_net* n, int steps, double lr, uint64_t seed, doub
   };
   rc = body();
   (void)hipStreamSynchronize(c->stream);
-  (void)hipFree(rs);
-  (void)hipFree(v);
-  (void)hipFree(pd);
   return rc;
 }
 
@@ -497,14 +491,14 @@ int lc_learned_guess(lc_ctx* c, const double* w, double* phi0, double* eps) {
   double n0 = 0.0;
   if ((rc = vnorm_div(c, w, c->r, &n0))) return rc;
   if (!std::isfinite(n0)) return fail(c, LC_EINVAL, "non-finite input");
-  double* v = nullptr;
-  if (hipMalloc(&v, c->nvel * sizeof(double)) != hipSuccess) return fail(c, LC_ENOMEM, "cannot allocate");
+  double* v = nullptr;  // the guessed start velocity (discarded): one vector of the Krylov workspace
+  long ld = 0;
+  if ((rc = krylov_ws(c, 1, &v, &ld))) return rc;
   bool used = false;
   double e = 1.0;
   rc = n0 > 0.0 ? learned_start(c, w, v, phi0, &used, &e) : LC_OK;
   if (!rc && !used) rc = hipMemsetAsync(phi0, 0, c->ncell * sizeof(double), c->stream) ? LC_EHIP : LC_OK;
   (void)hipStreamSynchronize(c->stream);
-  (void)hipFree(v);
   if (eps) *eps = used ? e : 1.0;
   return rc;
 }

@@ -129,3 +129,27 @@ def test_arnoldi_mixed_projection_leading_eigenvalue():
     err = rel_match(out["eig"], ref)
     print("mixed Arnoldi rel. err:", err)
     assert out["converged"] and err < 1e-6
+
+
+def test_arnoldi_learned_form_leading_eigenvalues():
+    # the learned form inside Arnoldi: every Krylov vector starts from the network's guess
+    # (an untrained seeded network; a guess that does not lower the divergence falls back to
+    # the plain start) and then runs mixed passes to the projection tolerance; its fixed
+    # point is the plain one, so the leading eigenvalues must match the dense spectrum to 1e-6
+    import paper_1704_08521_amd as lk
+    g = Grid.make(8)
+    U, _ = Newton(g, 100.0, 0.0).solve(tol=1e-13)
+    c = ctx(8, 8, 8, "uniform", 100.0, 0.0)
+    c.set_base_flow(dev(U))
+    net = lk.Net(seed=5)
+    c.set_net(net)
+    out = c.arnoldi_leading(k=4, m=20, tol=1e-9, max_restarts=300, seed=3, precision=lk.LEARNED, proj_tol=1e-10,
+                            vectors=True)
+    ref = gold("spectrum_8_uniform_re100_a0.txt")[: len(out["eig"]) + 1]
+    err = rel_match(out["eig"], ref)
+    print("learned Arnoldi rel. err:", err, "vectors", out["n_vectors"])
+    assert out["converged"] and err < 1e-6
+    vre, vim = out["vectors"]
+    for q in range(len(out["eig"])):
+        x = host(vre[q]) + 1j * host(vim[q])
+        assert eigen.ritz_residual(g, U, 100.0, out["eig"][q], x) < 1e-6

@@ -297,34 +297,41 @@ def test_poisson_solve_each_route_asymmetric_grids(case, method):
 @pytest.mark.parametrize("n", [1000, 513, 300, 128, 100, 65])
 def test_tpt_line_lengths(n):
     # every rows-per-lane instance of the tridiagonal pass (2 rows: 65-128 cells, 8: 257-512,
-    # 16: 513-1024; 1 and 4 are covered by the grids above) against TPF on a thin grid
+    # 16: 513-1024; 1 and 4 are covered by the grids above) and the x transforms of the TPF
+    # route on a thin grid, each against the oracle's exact solve
     c, g, _ = ctx_for(n, 3, 4, "tanh")
     r = synth.random_cells(n, 3, 4, 17)
     V = g.volumes()
     r = r - np.sum(V * r) / np.sum(V)
+    ref = poisson.PoissonFD(g).solve(r).ravel()
     rd = dev(r.ravel())
     c.set_poisson_method("tpf")
     phi_f = host(c.poisson_solve(rd))
     c.set_poisson_method("tpt")
     phi_t = host(c.poisson_solve(rd))
-    assert rel(phi_t, phi_f) < 1e-10
+    print(f"n={n}: tpt {rel(phi_t, ref):.2e} tpf {rel(phi_f, ref):.2e}")
+    # both sides round n-term inner products along the long line: 1e-13 n beyond n = 100
+    # (the derivation is in test_gpu_instances)
+    bound = max(1e-11, 1e-13 * n)
+    assert rel(phi_t, ref) < bound and rel(phi_f, ref) < bound
 
 
 def test_routes_agree_full_size_200():
-    # the benchmark's workload: TPT against TPF on the same right side, and the TPT
-    # Krylov vector against the oracle, full fields
+    # the benchmark's workload: TPT and TPF on the same right side against the oracle's
+    # solve, and the TPT Krylov vector against the oracle, full fields
     nx = 200
     c, g, U = ctx_for(nx, nx, nx, "tanh", re=1900.0, alpha=0.0, seed=11)
     r = synth.random_cells(nx, nx, nx, 13)
     V = g.volumes()
     r = r - np.sum(V * r) / np.sum(V)
     rd = dev(r.ravel())
+    ref = poisson.PoissonFD(g).solve(r).ravel()
     c.set_poisson_method("tpf")
     phi_f = host(c.poisson_solve(rd))
     c.set_poisson_method("tpt")
     phi_t = host(c.poisson_solve(rd))
-    print(f"TPT vs TPF at 200^3: {rel(phi_t, phi_f):.3e}")
-    assert rel(phi_t, phi_f) < 1e-11
+    print(f"at 200^3: TPT vs oracle {rel(phi_t, ref):.3e}, TPF vs oracle {rel(phi_f, ref):.3e}")
+    assert rel(phi_t, ref) < 1e-11 and rel(phi_f, ref) < 1e-11
     v = synth.random_velocity(nx, nx, nx, 12)
     vo, _, st = c.krylov_vector(dev(v), tol=1e-8)
     assert st["converged"] and st["rho"] <= 1e-8

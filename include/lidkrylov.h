@@ -409,6 +409,19 @@ int lc_learned_guess(lc_ctx* ctx, const double* w, double* phi0, double* eps);
 /* Euclidean dot product of two velocity vectors (host result). */
 int lc_dot(lc_ctx* ctx, const double* a, const double* b, double* out);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): lc_dot without a context.  out (host)
+ * = sum a[i] b[i] over n doubles (device, 8-byte aligned), enqueued on hip_stream
+ * (hipStream_t, NULL = default) and synchronized; bit-identical to lc_dot on a context
+ * whose lc_vel_size() is n (same block partial sums, same fixed-order final sum).
+ * Allocates nothing: the at most 4096 partial sums and the result live in a 33 KB
+ * file-scope device array, one per GPU, held until the process ends.  Every call on a
+ * GPU shares that array, so calls that overlap on one GPU (several streams or host
+ * threads) race; serialize them.  LC_EINVAL for null or misaligned pointers, n < 1 or
+ * n > LC_NOALLOC_MAX_N; LC_EHIP for a HIP error. */
+#define LC_NOALLOC_MAX_N (1ull << 36)
+int lc_dot_noalloc(const double* a, const double* b, size_t n, double* out, void* hip_stream);
+
 /* ---------------------------------------------------------------- profiling */
 
 /* Kernel classes timed by the profiling mode. */

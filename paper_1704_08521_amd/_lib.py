@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(HERE, "liblidkrylov.so")
 LC_OK, LC_ENOTCONV, LC_EINVAL, LC_ESTATE, LC_EHIP, LC_ENOMEM = 0, 1, -1, -2, -3, -4
 UNIFORM, SINE, TANH = 0, 1, 2
 FP64, MIXED, LEARNED = 0, 1, 2
+NOALLOC_MAX_N = 1 << 36  # LC_NOALLOC_MAX_N
 
 
 class LidKrylovError(RuntimeError):
@@ -70,6 +71,7 @@ _SIGS = {
     "lc_project": (_I, [_P, _P, _P, _P, _I, _D, _I, C.POINTER(Stats)]),
     "lc_krylov_vector": (_I, [_P, _P, _P, _P, _I, _D, _I, C.POINTER(Stats)]),
     "lc_dot": (_I, [_P, _P, _P, C.POINTER(_D)]),
+    "lc_dot_noalloc": (_I, [_P, _P, C.c_size_t, C.POINTER(_D), _P]),
     "lc_axis_modes": (_I, [_I, _P, _P, _P, _P]),
     "lc_hessenberg_eigvals": (_I, [_I, _P, _P, _P]),
     "lc_newton_residual": (_I, [_P, _P, C.POINTER(_D)]),

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "liblidkrylov.so")
 SOURCES = ["lk_stencil.hip", "lk_transform.hip", "lk_kernels.hip", "lk_nn.hip", "lk_api.cpp", "lk_krylov.cpp",
            "lk_linalg.cpp", "lk_nn_host.cpp", "lk_planes.hip", "lk_planes_host.cpp",
-           "lk_tpt.hip", "lk_modes.cpp", "lk_stokes.cpp"]
+           "lk_tpt.hip", "lk_modes.cpp", "lk_stokes.cpp", "lk_noalloc.hip"]
 ARCH = os.environ.get("LK_OFFLOAD_ARCH", "gfx950")
 
 # -packed-fp32-ops: never emit packed FP32 arithmetic (v_pk_*_f32)

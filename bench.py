@@ -12,7 +12,7 @@ passes).
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--size 200] [--no-cpu]
                     [--train-steps 300] [--poisson tpt|tpf]
-    python bench.py --planes | --critical N
+    python bench.py --planes | --critical N[,N...]
 """
 from __future__ import annotations
 
@@ -45,7 +45,7 @@ def parse():
     ap.add_argument("--cpu-reps", type=int, default=3, help="timed oracle Krylov vectors (after one warm-up)")
     ap.add_argument("--train-steps", type=int, default=300, help="Adam steps of the learned guess (64^3 pairs)")
     ap.add_argument("--train-size", type=int, default=64)
-    ap.add_argument("--critical", type=int, default=0, metavar="N",
+    ap.add_argument("--critical", type=str, default="", metavar="N[,N...]",
                     help="instead of the Krylov-vector benchmark: critical Reynolds number of the N^3 cube "
                          "on the sine grid of eq. 5, lid along x (Newton continuation, then the secant "
                          "driver lc_critical_re); one JSON line")
@@ -312,44 +312,64 @@ def planes_run(n, lk, torch, steps, route):
     print(json.dumps(res), flush=True)
 
 
-def critical_run(n, lk, torch):
-    """Steady states continued from rest up to Re = 1930, then the secant search for the
-    critical Reynolds number (the leading eigenvalue of eq. 7 crossing the imaginary
-    axis) from Re = 1940 and 1990.  The continuation and driver settings were chosen
-    for the 100^3 grid."""
+def critical_one(n, lk, torch, alpha_deg=0.0):
+    """One grid: steady states continued from rest with Stokes-preconditioned Newton up to
+    Re = 1900, then the secant search for the critical Reynolds number (the leading
+    eigenvalue of eq. 7 crossing the imaginary axis) from Re = 1920 and 1960."""
+    import math
     ctx = lk.Context(n)
     ctx.set_stretching("sine", 0.0)
-    ctx.set_lid(0.0)
+    ctx.set_lid(math.radians(alpha_deg))
     ctx.set_base_flow(torch.zeros(ctx.nvel, dtype=torch.float64, device="cuda"))
+    ctx.set_stokes_precond(float("inf"))
     t0 = time.perf_counter()
     cont = []
-    for re in (250.0, 500.0, 800.0, 1100.0, 1400.0, 1600.0, 1750.0, 1850.0, 1930.0):
+    vectors = 0
+    for re in (250.0, 500.0, 800.0, 1100.0, 1400.0, 1600.0, 1750.0, 1850.0, 1900.0):
         ctx.set_re(re)
-        for step in range(9):
+        for step in range(12):
             _, r = ctx.newton_residual()
-            log(f"[critical] Re {re:g} Newton step {step}: |P R(U)| {r:.2e} ({time.perf_counter() - t0:.0f} s)")
-            if r <= 1e-9 or step == 8:
+            log(f"[critical {n}] Re {re:g} Newton step {step}: |P R(U)| {r:.2e} ({time.perf_counter() - t0:.0f} s)")
+            if r <= 1e-11 or step == 11:
                 break
-            ctx.newton_step(lin_tol=1e-9, gmres_m=100, max_vectors=20000)
+            vectors += ctx.newton_step(lin_tol=1e-8, gmres_m=100, max_vectors=20000)["n_vectors"]
         cont.append({"re": re, "newton_steps": step, "res_inf": r})
     t1 = time.perf_counter()
     os.environ["LK_VERBOSE"] = "1"  # progress trace on stderr during the long driver call
-    out = ctx.critical_re(1940.0, 1990.0, re_tol=2e-5, max_evals=5, newton_tol=1e-9, newton_steps=6,
-                          lin_tol=1e-9, gmres_m=100, max_vectors=20000, k=8, m=100, eig_tol=1e-6,
-                          max_restarts=120, seed=1)
+    out = ctx.critical_re(1920.0, 1960.0, re_tol=1e-6, max_evals=7, newton_tol=1e-11, newton_steps=8,
+                          lin_tol=1e-8, gmres_m=100, max_vectors=20000, k=8, m=100, eig_tol=1e-8,
+                          max_restarts=150, seed=1, warm_start=True)
     os.environ["LK_VERBOSE"] = "0"
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    res = {"metric": "critical Reynolds number (leading eigenvalue of eq. 7 crossing the imaginary axis)",
-           "grid": [n, n, n], "stretching": "sine (eq. 5)", "alpha_deg": 0.0, "re_cr": out["re_cr"],
-           "omega_cr": out["omega_cr"], "converged": out["converged"],
+    ctx.close()
+    res = {"grid": [n, n, n], "re_cr": out["re_cr"], "omega_cr": out["omega_cr"], "converged": out["converged"],
            "evaluations": [{"re": h[0], "re_lambda": h[1], "im_lambda": h[2], "res_inf": h[3]}
                            for h in out["history"]],
-           "continuation": cont, "seconds_continuation": t1 - t0, "seconds_critical": t2 - t1}
-    if n in PAPER_TABLE3_A0:
+           "continuation": cont, "continuation_krylov_vectors": vectors,
+           "seconds_continuation": t1 - t0, "seconds_critical": t2 - t1}
+    if n in PAPER_TABLE3_A0 and alpha_deg == 0.0:
         pre, pom = PAPER_TABLE3_A0[n]
         res["paper_table3"] = {"re_cr": pre, "omega_cr": pom, "re_rel_diff": out["re_cr"] / pre - 1.0,
                                "omega_rel_diff": out["omega_cr"] / pom - 1.0}
+    return res
+
+
+def critical_run(sizes, lk, torch):
+    """Critical Reynolds number on each grid of the sequence (sine grid of eq. 5, lid along
+    x) and the Richardson extrapolation of Section 5 from each pair of consecutive grids:
+    with an O(h^2) error, v = v_f + (v_f - v_c) / ((n_f / n_c)^2 - 1)."""
+    grids = [critical_one(n, lk, torch) for n in sizes]
+    extrap = []
+    for c, f in zip(grids, grids[1:]):
+        nc, nf = c["grid"][0], f["grid"][0]
+        q = (nf / nc) ** 2 - 1.0
+        extrap.append({"grids": [nc, nf], "re_cr": f["re_cr"] + (f["re_cr"] - c["re_cr"]) / q,
+                       "omega_cr": f["omega_cr"] + (f["omega_cr"] - c["omega_cr"]) / q})
+    res = {"metric": "critical Reynolds number (leading eigenvalue of eq. 7 crossing the imaginary axis)",
+           "stretching": "sine (eq. 5)", "alpha_deg": 0.0, "newton": "Stokes-preconditioned (dt = inf)",
+           "grids": grids, "richardson": extrap,
+           "paper_table3_extrapolated": {"re_cr": 1919.37, "omega_cr": 0.58607}}
     print(json.dumps(res), flush=True)
 
 
@@ -363,7 +383,7 @@ def main():
     import paper_1704_08521_amd as lk
     if a.critical:
         torch.cuda.set_device(0)
-        critical_run(a.critical, lk, torch)
+        critical_run([int(x) for x in a.critical.split(",")], lk, torch)
         return
     if a.planes:
         torch.cuda.set_device(0)
@@ -380,6 +400,18 @@ def main():
     U = synthetic_base_flow(ctx, torch)
     ctx.set_base_flow(U)
     inputs = make_inputs(ctx, torch, a.warmup + a.steps)
+    # the streaming ceiling of this device for the stencil's pattern (2 reads + 1 write) and
+    # for a copy: plain 16-byte-access kernels over velocity-sized arrays
+    import ctypes
+    lib = lk._lib.load()
+    ceiling = {}
+    for kind, name in ((1, "read2_write1"), (0, "copy"), (2, "read")):
+        tb, us = ctypes.c_double(), ctypes.c_double()
+        rc = lib.lc_stream_probe(kind, ctypes.c_size_t(8 * ctx.nvel), 20, ctypes.c_void_p(
+            torch.cuda.current_stream().cuda_stream), ctypes.byref(tb), ctypes.byref(us))
+        if rc == 0:
+            ceiling[name] = {"TB/s": tb.value, "us": us.value, "frac_of_peak": tb.value * 1e3 / PEAK_HBM_GBS}
+    log(f"[bench] streaming ceiling: " + ", ".join(f"{k} {v['TB/s']:.2f} TB/s" for k, v in ceiling.items()))
     # calibration for hardware byte counters: one plain device copy of 256 MiB
     calib = torch.empty(1 << 25, dtype=torch.float64, device="cuda")
     calib.copy_(inputs[0][: 1].expand(1 << 25))
@@ -413,6 +445,8 @@ def main():
     for name in ("mixed", "learned"):
         forms[name]["rel_diff_vs_plain"] = float(torch.linalg.vector_norm(outs[name] - ref) /
                                                  torch.linalg.vector_norm(ref))
+        # the measured quantity of each form against plain: time per vector (> 1: slower)
+        forms[name]["time_vs_plain"] = forms[name]["ms_per_step"] / forms["plain"]["ms_per_step"]
 
     # profiled repeat of the plain timed loop: per-kernel HIP events on the context stream
     ctx.profile(True)
@@ -445,6 +479,10 @@ def main():
         t = profile_traffic(name, n)
         if t is not None:
             row["traffic"] = t
+    if roof["bound"] == "hbm" and "read2_write1" in ceiling:
+        # the same kernel against what a plain kernel with its access pattern reaches here
+        roof["ceiling"] = ceiling["read2_write1"]["TB/s"] * 1e3
+        roof["frac_of_ceiling"] = roof["achieved"] / roof["ceiling"]
 
     log("[bench] Arnoldi cycle (m=30, k=6, one restart)")
     arnoldi = time_arnoldi(ctx, lk, torch)
@@ -472,6 +510,7 @@ def main():
         "arnoldi": arnoldi,
         "planes": planes,
         "roofline": roof,
+        "stream_ceiling": ceiling,
         "kernels": table,
     }
     if not a.no_cpu:

@@ -120,10 +120,15 @@ int lc_set_re(lc_ctx* ctx, double re);
 /* Lid direction: u = cos(alpha), v = sin(alpha) at z = 1 (Section 2, eq. 4). */
 int lc_set_lid(lc_ctx* ctx, double alpha_rad);
 
-/* Base flow U (velocity, device) about which eq. 6 is linearized; copied. */
+/* Base flow U (velocity, device) about which eq. 6 is linearized; copied.  The base-flow
+ * pressure enters the equations linearly, so the linearized operator does not depend on
+ * it and it is not an input; lc_get_base_flow computes it from U. */
 int lc_set_base_flow(lc_ctx* ctx, const double* U);
-/* Copy the base flow out (velocity, device). */
-int lc_get_base_flow(const lc_ctx* ctx, double* U);
+/* Copy the base flow out (velocity, device).  P (cell, device, may be NULL) receives the
+ * pressure of the steady equations at U: the P with R(U) - G P divergence-free and
+ * sum V P = 0 (R the residual of lc_residual; at a steady state R(U) = G P), by one exact
+ * projection (uses the work vector and one Krylov vector). */
+int lc_get_base_flow(lc_ctx* ctx, double* U, double* P);
 
 /* ---------------------------------------------------------------- stencils */
 
@@ -215,8 +220,10 @@ int lc_newton_step(lc_ctx* ctx, double lin_tol, int gmres_m, long max_vectors, i
 
 /* Leading eigenvalues of the stability problem (eq. 7): the k eigenvalues of
  * P L_U with largest real part, by implicitly restarted Arnoldi on
- * SIMPLE-evaluated Krylov vectors started from a seeded (SplitMix64, `seed`)
- * random vector projected onto the divergence-free space.  Each extension
+ * SIMPLE-evaluated Krylov vectors started from v0 (velocity, device; NULL: a seeded
+ * SplitMix64 uniform field of stream `seed`) projected onto the divergence-free space.
+ * A start close to the wanted eigenvectors (the last ones of a nearby Re) shortens the
+ * iteration; the seeded field also sets the divergence scale of the test below.  Each extension
  * orthogonalizes by classical Gram-Schmidt in float64 (repeated once when the
  * norm drops below 1/sqrt 2 of its value); the m x m Hessenberg eigenproblem
  * is solved in float64 on the host and the m - k unwanted Ritz values serve as
@@ -236,7 +243,7 @@ int lc_newton_step(lc_ctx* ctx, double lin_tol, int gmres_m, long max_vectors, i
  * without convergence (outputs hold the last Ritz values).  Workspace:
  * 2 (m + 1) velocity vectors (library-owned). */
 int lc_arnoldi_leading(lc_ctx* ctx, int k, int m, double tol, int max_restarts, unsigned long long seed,
-                       int precision, double proj_tol, double* eig_re, double* eig_im, double* resid,
+                       const double* v0, int precision, double proj_tol, double* eig_re, double* eig_im, double* resid,
                        double* vec_re, double* vec_im, int* n_out, long* n_vectors);
 
 /* ------------------------------------ Stokes-preconditioned Krylov vectors */
@@ -292,6 +299,8 @@ typedef struct {
   double eig_tol;
   int max_restarts;
   unsigned long long seed;
+  int warm_start;         /* 1: Arnoldi after the first evaluation starts from the last     */
+                          /* leading eigenvector (see below); 0: every one from `seed`      */
 } lc_critical_opts;
 
 /* Critical Reynolds number of the context's grid and lid direction (Section 2, the
@@ -301,8 +310,12 @@ typedef struct {
  * driver uses the secant method on Re -> Re Lambda(Re) from re0 and re1.  Each
  * evaluation sets Re, starts from the context's base flow (first evaluation) or from
  * the linear extrapolation in Re of the last two steady states, runs Newton steps
- * (lc_newton_step) until max |P R(U)| <= newton_tol or newton_steps, then
- * lc_arnoldi_leading (LC_ENOTCONV there is accepted: its last Ritz values are used).
+ * (lc_newton_step, preconditioned as lc_set_stokes_precond says) until max |P R(U)| <=
+ * newton_tol or newton_steps, then lc_arnoldi_leading (LC_ENOTCONV there is accepted: its
+ * last Ritz values are used), from the seeded random field the first time and afterwards
+ * (warm_start = 1)
+ * from the previous leading eigenvector (real plus imaginary part) plus a seeded random
+ * part of relative size 1e-3.
  * The context's base flow should be a steady state (or a good guess) at re0; on
  * return it holds the last steady state and Re the last evaluated value.
  * Outputs (host): re_cr, omega_cr (|Im Lambda| interpolated linearly in Re between the
@@ -311,8 +324,8 @@ typedef struct {
  * evaluations did not meet re_tol; re_cr and omega_cr then come from the linear root
  * between the evaluations closest to zero on either side (largest negative and
  * smallest positive Re Lambda) when both exist, else from the last secant iterate.
- * Workspace: three velocity vectors (the stored steady states and a residual) plus
- * those of Newton and Arnoldi (library-owned). */
+ * Workspace: six velocity vectors (the stored steady states, a residual, the leading
+ * eigenvector and the next start) plus those of Newton and Arnoldi. */
 int lc_critical_re(lc_ctx* ctx, double re0, double re1, const lc_critical_opts* opt, double* re_cr,
                    double* omega_cr, double* hist, int* n_evals);
 
@@ -453,6 +466,15 @@ int lc_profile_read(lc_ctx* ctx, int kernel_class, double* total_ms, long* launc
 
 /* Name of a kernel class (static storage), NULL if out of range. */
 const char* lc_profile_name(int kernel_class);
+
+/* Streaming ceiling of the current device, the reference the stencil kernels' bandwidth is
+ * judged against: a plain kernel with 16-byte accesses over arrays of `bytes` each
+ * (>= 4096), kind 0 copy (1 read + 1 write), 1 two reads + one write (the momentum
+ * stencil's pattern), 2 read only; 3 warm-up launches, then `reps` timed by HIP events on
+ * hip_stream (hipStream_t, NULL = default).  tbps (host) = bytes moved per launch / mean
+ * launch time, in TB/s; us (host, may be NULL) the mean launch time.  Allocates (and frees)
+ * three arrays.  LC_EINVAL for bad arguments, LC_ENOMEM, LC_EHIP. */
+int lc_stream_probe(int kind, size_t bytes, int reps, void* hip_stream, double* tbps, double* us);
 
 #ifdef __cplusplus
 }

@@ -127,10 +127,14 @@ class Context:
     def set_base_flow(self, U):
         self._check(self.lib.lc_set_base_flow(self._h, self._ptr(U, self.nvel, "U")))
 
-    def get_base_flow(self, out=None):
+    def get_base_flow(self, out=None, pressure=False):
+        """The base flow U (a copy); with pressure=True also (U, P), P the pressure of the
+        steady equations at U (R(U) - G P divergence-free, volume mean zero)."""
         out = self.vel() if out is None else out
-        self._check(self.lib.lc_get_base_flow(self._h, self._ptr(out, self.nvel, "U")))
-        return out
+        P = self.cells() if pressure else None
+        self._check(self.lib.lc_get_base_flow(self._h, self._ptr(out, self.nvel, "U"),
+                                              None if P is None else self._ptr(P, self.ncell, "P")))
+        return (out, P) if pressure else out
 
     # ------------------------------------------------------------ stencils
     def jacobian_apply(self, v, out=None):
@@ -263,8 +267,9 @@ class Context:
         return hist
 
     def arnoldi_leading(self, k=4, m=20, tol=1e-10, max_restarts=200, seed=1, precision=FP64, proj_tol=1e-12,
-                        vectors=False):
-        """Leading eigenvalues (largest real part) of eq. 7 by implicitly restarted Arnoldi."""
+                        vectors=False, start=None):
+        """Leading eigenvalues (largest real part) of eq. 7 by implicitly restarted Arnoldi,
+        started from the velocity `start` (projected) or from a seeded random field."""
         torch = _torch()
         re = np.zeros(k + 1); im = np.zeros(k + 1); res = np.zeros(k + 1)
         vre = vim = None
@@ -274,7 +279,8 @@ class Context:
         nout, nvec = C.c_int(), C.c_long()
         p = lambda a: a.ctypes.data_as(C.c_void_p)
         rc = self._check(self.lib.lc_arnoldi_leading(
-            self._h, int(k), int(m), float(tol), int(max_restarts), C.c_ulonglong(seed), int(precision),
+            self._h, int(k), int(m), float(tol), int(max_restarts), C.c_ulonglong(seed),
+            None if start is None else self._ptr(start, self.nvel, "start"), int(precision),
             float(proj_tol), p(re), p(im), p(res), C.c_void_p(vre.data_ptr()) if vectors else None,
             C.c_void_p(vim.data_ptr()) if vectors else None, C.byref(nout), C.byref(nvec)), allow_notconv=True)
         n = nout.value
@@ -284,11 +290,13 @@ class Context:
         return out
 
     def critical_re(self, re0, re1, re_tol=1e-8, max_evals=12, newton_tol=1e-10, newton_steps=12, lin_tol=1e-10,
-                    gmres_m=100, max_vectors=5000, k=6, m=40, eig_tol=1e-10, max_restarts=400, seed=1):
+                    gmres_m=100, max_vectors=5000, k=6, m=40, eig_tol=1e-10, max_restarts=400, seed=1,
+                    warm_start=False):
         """Critical Reynolds number and frequency: secant on the real part of the leading
         eigenvalue from re0, re1 (the base flow should be a steady state at re0)."""
         o = CriticalOpts(float(re_tol), int(max_evals), float(newton_tol), int(newton_steps), float(lin_tol),
-                         int(gmres_m), int(max_vectors), int(k), int(m), float(eig_tol), int(max_restarts), int(seed))
+                         int(gmres_m), int(max_vectors), int(k), int(m), float(eig_tol), int(max_restarts), int(seed),
+                         int(bool(warm_start)))
         rc_, om = C.c_double(), C.c_double()
         ne = C.c_int()
         hist = np.zeros(4 * max(int(max_evals), 2))

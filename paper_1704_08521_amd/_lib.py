@@ -28,7 +28,7 @@ class CriticalOpts(C.Structure):
     _fields_ = [("re_tol", C.c_double), ("max_evals", C.c_int), ("newton_tol", C.c_double),
                 ("newton_steps", C.c_int), ("lin_tol", C.c_double), ("gmres_m", C.c_int),
                 ("max_vectors", C.c_long), ("k", C.c_int), ("m", C.c_int), ("eig_tol", C.c_double),
-                ("max_restarts", C.c_int), ("seed", C.c_ulonglong)]
+                ("max_restarts", C.c_int), ("seed", C.c_ulonglong), ("warm_start", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -62,7 +62,7 @@ _SIGS = {
     "lc_set_re": (_I, [_P, _D]),
     "lc_set_lid": (_I, [_P, _D]),
     "lc_set_base_flow": (_I, [_P, _P]),
-    "lc_get_base_flow": (_I, [_P, _P]),
+    "lc_get_base_flow": (_I, [_P, _P, _P]),
     "lc_jacobian_apply": (_I, [_P, _P, _P]),
     "lc_residual": (_I, [_P, _P, _P]),
     "lc_divergence": (_I, [_P, _P, _P, C.POINTER(_D)]),
@@ -77,7 +77,7 @@ _SIGS = {
     "lc_newton_residual": (_I, [_P, _P, C.POINTER(_D)]),
     "lc_newton_step": (_I, [_P, _D, _I, C.c_long, _I, _D, C.POINTER(_D), C.POINTER(_D), C.POINTER(C.c_long),
                             C.POINTER(_I)]),
-    "lc_arnoldi_leading": (_I, [_P, _I, _I, _D, _I, C.c_ulonglong, _I, _D, _P, _P, _P, _P, _P, C.POINTER(_I),
+    "lc_arnoldi_leading": (_I, [_P, _I, _I, _D, _I, C.c_ulonglong, _P, _I, _D, _P, _P, _P, _P, _P, C.POINTER(_I),
                                 C.POINTER(C.c_long)]),
     "lc_critical_re": (_I, [_P, _D, _D, C.POINTER(CriticalOpts), C.POINTER(_D), C.POINTER(_D), _P,
                             C.POINTER(_I)]),
@@ -98,6 +98,7 @@ _SIGS = {
     "lc_stokes_step": (_I, [_P, _P, _P, _D, _I, _D, _I, C.POINTER(Stats)]),
     "lc_stokes_vector": (_I, [_P, _P, _P, _D, _I, _D, _I, C.POINTER(Stats)]),
     "lc_set_stokes_precond": (_I, [_P, _D]),
+    "lc_stream_probe": (_I, [_I, C.c_size_t, _I, _P, C.POINTER(_D), C.POINTER(_D)]),
     "lc_profile_enable": (_I, [_P, _I]),
     "lc_profile_read": (_I, [_P, _I, C.POINTER(_D), C.POINTER(C.c_long)]),
     "lc_profile_name": (C.c_char_p, [_I]),

@@ -392,7 +392,7 @@ bool carve_all(lc_ctx* c) {
          ctx_alloc(c, &c->stokes_mem, viscous_bytes(nx, ny, nz)) == hipSuccess &&
          dalloc(c, &c->vscale, 2 * ((size_t)nx + ny + nz) + 3) == hipSuccess &&
          dalloc(c, &c->hs, component_max(nx, ny, nz)) == hipSuccess &&
-         dalloc(c, &c->ucr, 3 * c->nvel) == hipSuccess;
+         dalloc(c, &c->ucr, kCriticalVectors * c->nvel) == hipSuccess;
 }
 
 int create(lc_ctx** out, int nx, int ny, int nz, void* ws, size_t ws_bytes, void* hip_stream) {
@@ -567,11 +567,24 @@ int lc_set_base_flow(lc_ctx* c, const double* U) {
   return LC_OK;
 }
 
-int lc_get_base_flow(const lc_ctx* c, double* U) {
-  if (!c || !aligned(U)) return LC_EINVAL;
-  lc_ctx* m = const_cast<lc_ctx*>(c);
-  HIPCHK(m, hipMemcpyAsync(U, c->U, c->nvel * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-  HIPCHK(m, hipStreamSynchronize(c->stream));
+int lc_get_base_flow(lc_ctx* c, double* U, double* P) {
+  if (!c || !aligned(U) || (P && !aligned(P))) return fail(c, LC_EINVAL, "bad pointers");
+  HIPCHK(c, hipMemcpyAsync(U, c->U, c->nvel * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  if (P) {
+    // the pressure of the steady equations: R(U) - G P divergence-free, sum V P = 0 (at a
+    // steady state R(U) = G P); the projection's velocity goes to one Krylov vector
+    int rc = check_ready(c);
+    if (rc) return rc;
+    double* tmp = nullptr;
+    long ld = 0;
+    if ((rc = krylov_ws(c, 1, &tmp, &ld))) return rc;
+    KLAUNCH(c, LC_K_RESIDUAL, launch_momentum(c->g, c->U, c->U, c->w, 1.0 / c->re, 0.5, true, std::cos(c->alpha),
+                                              std::sin(c->alpha), c->stream));
+    lc_stats st;
+    rc = lc_project(c, c->w, tmp, P, LC_FP64, 1e-13, 4, &st);
+    if (rc < 0) return rc;
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
   return LC_OK;
 }
 
@@ -756,6 +769,45 @@ extern "C" int lc_profile_read(lc_ctx* c, int k, double* total_ms, long* launche
   *total_ms = t;
   *launches = n;
   return LC_OK;
+}
+
+extern "C" int lc_stream_probe(int kind, size_t bytes, int reps, void* hip_stream, double* tbps, double* us) {
+  if (kind < 0 || kind > 2 || bytes < 4096 || reps < 1 || !tbps) return LC_EINVAL;
+  const size_t n2 = bytes / 16;
+  hipStream_t st = (hipStream_t)hip_stream;
+  double *a = nullptr, *b = nullptr, *c = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = LC_OK;
+  if (hipMalloc((void**)&a, n2 * 16) != hipSuccess || hipMalloc((void**)&b, n2 * 16) != hipSuccess ||
+      hipMalloc((void**)&c, n2 * 16 + 8) != hipSuccess) {
+    rc = LC_ENOMEM;
+  } else if (hipMemsetAsync(a, 0, n2 * 16, st) != hipSuccess || hipMemsetAsync(b, 0, n2 * 16, st) != hipSuccess ||
+             hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    rc = LC_EHIP;
+  } else {
+    double* sink = c + 2 * n2;
+    bool ok = true;
+    for (int w = 0; w < 3 && ok; ++w) ok = launch_probe(kind, a, b, c, n2, sink, st) == hipSuccess;
+    ok = ok && hipEventRecord(e0, st) == hipSuccess;
+    for (int r = 0; r < reps && ok; ++r) ok = launch_probe(kind, a, b, c, n2, sink, st) == hipSuccess;
+    ok = ok && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+    float ms = 0.f;
+    ok = ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+    if (!ok) {
+      rc = LC_EHIP;
+    } else {
+      const double moved = (kind == 0 ? 2.0 : kind == 1 ? 3.0 : 1.0) * (double)(n2 * 16);
+      const double t = (double)ms * 1e-3 / reps;
+      *tbps = moved / t / 1e12;
+      if (us) *us = t * 1e6;
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (a) (void)hipFree(a);
+  if (b) (void)hipFree(b);
+  if (c) (void)hipFree(c);
+  return rc;
 }
 
 extern "C" int lc_axis_modes(int n, const double* faces, double* lam, double* S, double* Wf) {

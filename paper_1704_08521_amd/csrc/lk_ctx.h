@@ -139,6 +139,9 @@ size_t metric_doubles(int nx, int ny, int nz);
 size_t viscous_bytes(int nx, int ny, int nz);
 size_t component_max(int nx, int ny, int nz);
 int krylov_vectors(int m);
+// Velocities the critical-Re driver keeps: two steady states, a residual, the last leading
+// eigenvector (real, imaginary part) and the next Arnoldi start.
+constexpr int kCriticalVectors = 6;
 // Krylov vectors: `nvec` velocities ld = lc_vel_size rounded up to 64 apart (grown on demand,
 // or the remainder of the caller's workspace: LC_ENOMEM when it holds fewer).
 int krylov_ws(lc_ctx* c, int nvec, double** p, long* ld);

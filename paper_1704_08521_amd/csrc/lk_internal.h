@@ -154,6 +154,11 @@ hipError_t launch_f2d(size_t n, const float* in, double* out, bool accumulate, h
 // Fill with the counter-based SplitMix64 uniform [-1, 1) stream `seed`.
 hipError_t launch_uniform(double* x, size_t n, uint64_t seed, hipStream_t st);
 
+// Streaming probe: kind 0 copies a to c, 1 writes c = a + 1.5 b, 2 reads a; n2 16-byte
+// elements.  sink: one device double (written only by a never-taken branch).
+hipError_t launch_probe(int kind, const double* a, const double* b, double* c, size_t n2, double* sink,
+                        hipStream_t st);
+
 // Zero the wall-normal faces of a packed velocity.
 hipError_t launch_zero_walls(double* vel, int nx, int ny, int nz, hipStream_t st);
 

@@ -297,5 +297,33 @@ hipError_t launch_zero_walls(double* vel, int nx, int ny, int nz, hipStream_t st
   return hipGetLastError();
 }
 
+// ------------------------------------------------------- streaming ceiling probe
+// Plain streaming kernels (16-byte accesses, one per thread) that bound what any kernel
+// with the same access pattern can reach: copy (1 read, 1 write), the momentum stencil's
+// 2 reads + 1 write, and read only.
+namespace {
+typedef double probe_d2 __attribute__((ext_vector_type(2)));
+__global__ void k_probe(int kind, const probe_d2* __restrict__ a, const probe_d2* __restrict__ b,
+                        probe_d2* __restrict__ c, size_t n, double* __restrict__ sink) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (kind == 0) {
+    c[i] = a[i];
+  } else if (kind == 1) {
+    c[i] = a[i] + 1.5 * b[i];
+  } else {
+    const probe_d2 x = a[i];
+    if (x.x + x.y == 12345.678) sink[0] = x.x;  // keeps the load; never true for the zero fill
+  }
+}
+}  // namespace
+
+hipError_t launch_probe(int kind, const double* a, const double* b, double* c, size_t n2, double* sink,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(k_probe, dim3(blocks_for(n2, 256)), dim3(256), 0, st, kind, (const probe_d2*)a,
+                     (const probe_d2*)b, (probe_d2*)c, n2, sink);
+  return hipGetLastError();
+}
+
 }  // namespace lk
 

@@ -143,31 +143,33 @@ extern "C" int lc_hessenberg_eigvals(int m, const double* H, double* re, double*
 }
 
 // ============================================================== Arnoldi
-extern "C" int lc_arnoldi_leading(lc_ctx* c, int k, int m, double tol, int max_restarts, unsigned long long seed,
-                                  int precision, double proj_tol, double* eig_re, double* eig_im, double* resid,
-                                  double* vec_re, double* vec_im, int* n_out, long* n_vectors) {
-  int rc = check_ready(c);
-  if (rc) return rc;
-  if (k < 1 || m < k + 3 || m > 100 || k + 2 > 48 || !eig_re || !eig_im || !n_out)
-    return fail(c, LC_EINVAL, "need 1 <= k, k + 3 <= m <= 100, k <= 46 and output arrays");
-  if ((vec_re && !aligned(vec_re)) || (vec_im && !aligned(vec_im)) || !(tol > 0.0) || max_restarts < 0)
-    return fail(c, LC_EINVAL, "bad argument");
+namespace {
+
+// Implicitly restarted Arnoldi (see lc_arnoldi_leading); the first `nvec` Ritz vectors go
+// to vec_re / vec_im (nvel apart).
+int arnoldi_run(lc_ctx* c, int k, int m, double tol, int max_restarts, unsigned long long seed, const double* v0,
+                int precision, double proj_tol, double* eig_re, double* eig_im, double* resid, double* vec_re,
+                double* vec_im, int nvec, int* n_out, long* n_vectors) {
   KMap K{precision, proj_tol, 8};
   Basis V, W;
-  rc = ensure_ws(c, 2 * (m + 1), &V);
+  int rc = ensure_ws(c, 2 * (m + 1), &V);
   if (rc) return rc;
   W.p = V.p + (size_t)(m + 1) * V.ld;
   W.ld = V.ld;
-  // start vector: seeded uniform [-1, 1), projected onto the divergence-free space
+  // divergence scale of a vector with no solenoidal structure (a seeded uniform [-1, 1)
+  // field): a Ritz vector whose relative divergence is a sizeable fraction of it is not an
+  // eigenvector of eq. 7 (see `spurious` below)
   KLAUNCH(c, LC_K_VECTOR, launch_uniform(W.at(0), c->nvel, seed, c->stream));
   KLAUNCH(c, LC_K_VECTOR, launch_zero_walls(W.at(0), c->nx, c->ny, c->nz, c->stream));
-  // divergence scale of a vector with no solenoidal structure (the raw start vector):
-  // a Ritz vector whose relative divergence is a sizeable fraction of it is not an
-  // eigenvector of eq. 7 (see `spurious` below)
   double dref = 0.0, wn = 0.0;
   if ((rc = vnorm_div(c, W.at(0), nullptr, &dref))) return rc;
   if ((rc = vdot(c, W.at(0), W.at(0), &wn))) return rc;
   dref /= std::max(vnorm(wn), 1e-300);
+  // start vector: that random field, or the caller's, projected onto the divergence-free space
+  if (v0) {
+    if ((rc = vcopy(c, v0, W.at(0)))) return rc;
+    KLAUNCH(c, LC_K_VECTOR, launch_zero_walls(W.at(0), c->nx, c->ny, c->nz, c->stream));
+  }
   lc_stats st;
   rc = lc_project(c, W.at(0), V.at(0), nullptr, LC_FP64, 1e-13, 4, &st);
   if (rc < 0) return rc;
@@ -322,7 +324,7 @@ extern "C" int lc_arnoldi_leading(lc_ctx* c, int k, int m, double tol, int max_r
     if (resid) resid[i] = res[i];
   }
   if (vec_re || vec_im) {  // Ritz vectors x_i = V_m y_i (unit norm)
-    for (int i = 0; i < kc; ++i) {
+    for (int i = 0; i < std::min(kc, nvec); ++i) {
       std::vector<double> Qy((size_t)m * 2);
       for (int r = 0; r < m; ++r) {
         Qy[(size_t)r * 2] = Y[i][r].real();
@@ -341,6 +343,22 @@ extern "C" int lc_arnoldi_leading(lc_ctx* c, int k, int m, double tol, int max_r
   if (n_vectors) *n_vectors = K.count;
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return converged ? LC_OK : LC_ENOTCONV;
+}
+
+}  // namespace
+
+extern "C" int lc_arnoldi_leading(lc_ctx* c, int k, int m, double tol, int max_restarts, unsigned long long seed,
+                                  const double* v0, int precision, double proj_tol, double* eig_re, double* eig_im,
+                                  double* resid, double* vec_re, double* vec_im, int* n_out, long* n_vectors) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  if (k < 1 || m < k + 3 || m > 100 || k + 2 > 48 || !eig_re || !eig_im || !n_out)
+    return fail(c, LC_EINVAL, "need 1 <= k, k + 3 <= m <= 100, k <= 46 and output arrays");
+  if ((vec_re && !aligned(vec_re)) || (vec_im && !aligned(vec_im)) || (v0 && !aligned(v0)) || !(tol > 0.0) ||
+      max_restarts < 0)
+    return fail(c, LC_EINVAL, "bad argument");
+  return arnoldi_run(c, k, m, tol, max_restarts, seed, v0, precision, proj_tol, eig_re, eig_im, resid, vec_re, vec_im,
+                     k + 1, n_out, n_vectors);
 }
 
 // ================================================================ Newton
@@ -588,10 +606,13 @@ extern "C" int lc_critical_re(lc_ctx* c, double re0, double re1, const lc_critic
   if (o->max_evals < 2 || o->newton_steps < 0 || !(o->re_tol > 0.0) || !(o->newton_tol > 0.0))
     return fail(c, LC_EINVAL, "bad critical-Re options");
   *n_evals = 0;
-  if (!c->ucr && dalloc(c, &c->ucr, 3 * c->nvel) != hipSuccess)
+  if (!c->ucr && dalloc(c, &c->ucr, kCriticalVectors * c->nvel) != hipSuccess)
     return fail(c, LC_ENOMEM, "cannot allocate the stored steady states");
   double* Us[2] = {c->ucr, c->ucr + c->nvel};  // the last two steady states, oldest first
   double* Fr = c->ucr + 2 * c->nvel;            // projected residual (scratch)
+  // the last leading eigenvector (real, imaginary part) and the next Arnoldi start
+  double *xr = c->ucr + 3 * c->nvel, *xi = c->ucr + 4 * c->nvel, *v0 = c->ucr + 5 * c->nvel;
+  bool have_vec = false;
   double Re_s[2] = {0.0, 0.0};
   int nstored = 0;
   std::vector<double> R, F, W;  // evaluations: Re, Re Lambda, |Im Lambda|
@@ -628,10 +649,22 @@ extern "C" int lc_critical_re(lc_ctx* c, double re0, double re1, const lc_critic
     nstored = std::min(nstored + 1, 2);
     int nout = 0;
     long nvec = 0;
-    r2 = lc_arnoldi_leading(c, o->k, o->m, o->eig_tol, o->max_restarts, o->seed, LC_FP64, 1e-12, er.data(),
-                            ei.data(), res.data(), nullptr, nullptr, &nout, &nvec);
+    // warm start after the first evaluation: the leading eigenvector changes little between
+    // nearby Re, so Arnoldi starts from its real plus imaginary part (spanning the pair's
+    // invariant subspace) plus a seeded random part of relative size 1e-3 that keeps every
+    // other direction present
+    const double* start = nullptr;
+    if (have_vec && o->warm_start) {
+      KLAUNCH(c, LC_K_VECTOR, launch_uniform(v0, c->nvel, o->seed + 7919ull * R.size(), c->stream));
+      if ((r2 = vscale(c, 1e-3 * std::sqrt(3.0 / (double)c->nvel), v0))) return r2;
+      if ((r2 = vaxpy(c, 1.0, xr, v0)) || (r2 = vaxpy(c, 1.0, xi, v0))) return r2;
+      start = v0;
+    }
+    r2 = arnoldi_run(c, o->k, o->m, o->eig_tol, o->max_restarts, o->seed, start, LC_FP64, 1e-12, er.data(),
+                     ei.data(), res.data(), xr, xi, 1, &nout, &nvec);
     if (r2 < 0) return r2;
     if (nout < 1) return fail(c, LC_ENOTCONV, "no Ritz values at Re = %g", re);
+    have_vec = true;
     int lead = 0;
     for (int i = 1; i < nout; ++i)
       if (er[i] > er[lead]) lead = i;

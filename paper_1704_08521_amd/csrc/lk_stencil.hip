@@ -11,8 +11,9 @@ namespace {
 // ------------------------------------------------------------------ momentum
 // One block owns a TX x TY column of (i, j) positions and marches along z over
 // a chunk of planes.  For each of the six input fields (advecting a = U and
-// advected b, components u, v, w) a ring of three planes k-1, k, k+1 with a
-// one-cell x/y halo lives in LDS.  Positions outside a field's stored range are
+// advected b, components u, v, w) the planes k and k+1 with a one-cell x/y halo live
+// in LDS (17 KB); the few plane k-1 values a step needs are carried in registers from
+// the step before.  Positions outside a field's stored range are
 // filled with the wall value of that position: 0 on wall-normal faces, beyond
 // tangential walls 0 or, for the advected field of the nonlinear residual, the
 // lid velocity at z = 1 (eq. 4).  With these ghosts the wall fluxes of the
@@ -36,7 +37,7 @@ __global__ void __launch_bounds__(TX* TY) k_momentum(GridDev g, const double* __
                                                     double s, double lid_u, double lid_v, int kchunk, int nbx,
                                                     int nby) {
   constexpr int MPX = TX + 2, MPY = TY + 2, MPS = MPX * MPY;
-  __shared__ double sm[6][3][MPS];  // 0..2: a (u, v, w); 3..5: b (u, v, w)
+  __shared__ double sm[6][2][MPS];  // 0..2: a (u, v, w); 3..5: b (u, v, w); planes k, k+1
   const int nx = g.x.n, ny = g.y.n, nz = g.z.n;
   const size_t nu = (size_t)(nx + 1) * ny * nz, nv = (size_t)nx * (ny + 1) * nz;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -91,7 +92,7 @@ __global__ void __launch_bounds__(TX* TY) k_momentum(GridDev g, const double* __
     }
   };
   auto store = [&](const double(&reg)[6][PER], int k) {
-    const int slot = (k + 3) % 3;
+    const int slot = (k + 2) & 1;
 #pragma unroll
     for (int arr = 0; arr < 6; ++arr) {
 #pragma unroll
@@ -111,19 +112,14 @@ __global__ void __launch_bounds__(TX* TY) k_momentum(GridDev g, const double* __
   const double rddy0 = (j <= ny) ? g.y.rdd[j] : 0.0, rddy1 = (j + 1 <= ny) ? g.y.rdd[j + 1] : 0.0;
 
   double cm[6], c0[6], cp[6];
+  double nm0, nm3, nm1, nm4;  // plane k-1: u-fields at (0, +1), v-fields at (+1, 0)
   auto compute = [&](int k) {
-    const int pm = (k + 2) % 3, p0 = k % 3, pp = (k + 1) % 3;  // planes k-1, k, k+1
+    const int p0 = (k + 2) & 1, pp = (k + 3) & 1;  // planes k, k+1
     // S(arr, plane, dj, di)
 #define S(arr, pl, dj, di) sm[arr][pl][(ty + 1 + (dj)) * MPX + (tx + 1 + (di))]
-    // own-column values of planes k-1 and k are carried in registers from the
-    // previous steps; only plane k+1's is read here
-    if (k == kb) {
-#pragma unroll
-      for (int arr = 0; arr < 6; ++arr) {
-        cm[arr] = S(arr, pm, 0, 0);
-        c0[arr] = S(arr, p0, 0, 0);
-      }
-    }
+    // own-column values of planes k-1 and k, and the four plane k-1 neighbours the z-momentum
+    // edges need, are carried in registers from the previous steps; only plane k+1's own
+    // column is read here
 #pragma unroll
     for (int arr = 0; arr < 6; ++arr) cp[arr] = S(arr, pp, 0, 0);
 
@@ -249,8 +245,8 @@ __global__ void __launch_bounds__(TX* TY) k_momentum(GridDev g, const double* __
           e0 = au * bw + bu * aw;
         }
         {
-          const double au = lerp(S(0, pm, 0, 1), S(0, p0, 0, 1), thz0);
-          const double bu = lerp(S(3, pm, 0, 1), S(3, p0, 0, 1), thz0);
+          const double au = lerp(nm0, S(0, p0, 0, 1), thz0);
+          const double bu = lerp(nm3, S(3, p0, 0, 1), thz0);
           const double aw = lerp(c0[2], S(2, p0, 0, 1), thx1);
           const double bw = lerp(c0[5], S(5, p0, 0, 1), thx1);
           e1 = au * bw + bu * aw;
@@ -265,8 +261,8 @@ __global__ void __launch_bounds__(TX* TY) k_momentum(GridDev g, const double* __
           e0 = av * bw + bv * aw;
         }
         {
-          const double av = lerp(S(1, pm, 1, 0), S(1, p0, 1, 0), thz0);
-          const double bv = lerp(S(4, pm, 1, 0), S(4, p0, 1, 0), thz0);
+          const double av = lerp(nm1, S(1, p0, 1, 0), thz0);
+          const double bv = lerp(nm4, S(4, p0, 1, 0), thz0);
           const double aw = lerp(c0[2], S(2, p0, 1, 0), thy1);
           const double bw = lerp(c0[5], S(5, p0, 1, 0), thy1);
           e1 = av * bw + bv * aw;
@@ -280,6 +276,10 @@ __global__ void __launch_bounds__(TX* TY) k_momentum(GridDev g, const double* __
       }
       out[nu + nv + ((size_t)k * ny + j) * nx + i] = val;
     }
+    nm0 = S(0, p0, 0, 1);
+    nm3 = S(3, p0, 0, 1);
+    nm1 = S(1, p0, 1, 0);
+    nm4 = S(4, p0, 1, 0);
 #undef S
 #pragma unroll
     for (int arr = 0; arr < 6; ++arr) {
@@ -288,17 +288,38 @@ __global__ void __launch_bounds__(TX* TY) k_momentum(GridDev g, const double* __
     }
   };
 
-  load(r0, kb - 1);
-  store(r0, kb - 1);
+  // LDS holds planes k and k+1 (two slots); plane kb - 1 passes through once for the values
+  // carried in registers.  The next plane is loaded into registers during a step and
+  // written to the freed slot after it.
+#define S(arr, pl, dj, di) sm[arr][pl][(ty + 1 + (dj)) * MPX + (tx + 1 + (di))]
+  {
+    const int sl = (kb + 1) & 1;  // plane kb - 1
+    load(r0, kb - 1);
+    store(r0, kb - 1);
+    __syncthreads();
+#pragma unroll
+    for (int arr = 0; arr < 6; ++arr) cm[arr] = S(arr, sl, 0, 0);
+    nm0 = S(0, sl, 0, 1);
+    nm3 = S(3, sl, 0, 1);
+    nm1 = S(1, sl, 1, 0);
+    nm4 = S(4, sl, 1, 0);
+    __syncthreads();
+  }
   load(r0, kb);
   store(r0, kb);
   load(r0, kb + 1);
+  store(r0, kb + 1);
+  __syncthreads();
+#pragma unroll
+  for (int arr = 0; arr < 6; ++arr) c0[arr] = S(arr, kb & 1, 0, 0);
+#undef S
+  if (kb + 2 <= ke) load(r0, kb + 2);
   for (int k = kb; k < ke; ++k) {
-    store(r0, k + 1);
-    __syncthreads();
-    if (k + 2 <= ke) load(r0, k + 2);
     compute(k);
     __syncthreads();
+    if (k + 2 <= ke) store(r0, k + 2);
+    __syncthreads();
+    if (k + 3 <= ke) load(r0, k + 3);
   }
 }
 

@@ -1,0 +1,45 @@
+"""The base-flow pressure returned by lc_get_base_flow against the oracle.
+
+P is the pressure of the steady equations at U (eqs. 1-2): R(U) - G P divergence-free with
+sum V P = 0, i.e. the pressure of the exact projection of the residual R(U); one exact
+projection, so 1e-10 relative like a Krylov vector.  At a Newton steady state R(U) = G P
+holds to the Newton residual.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import fv, simple
+from oracle.grid import Grid
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("case", [(12, 10, 9, "tanh", 600.0, 0.3), (16, 16, 16, "uniform", 100.0, 0.0)])
+def test_base_flow_pressure(case):
+    import torch
+    import paper_1704_08521_amd as lk
+    nx, ny, nz, kind, re, al = case
+    print(f"[case] {case}", flush=True)
+    c = lk.Context(nx, ny, nz)
+    c.set_stretching(kind, 10.0)
+    c.set_re(re)
+    c.set_lid(al)
+    g = Grid.make(nx, ny, nz, kind=kind)
+    U = synth.random_velocity(nx, ny, nz, 71)
+    c.set_base_flow(torch.from_numpy(U).cuda())
+    Ug, P = c.get_base_flow(pressure=True)
+    _, phi = simple.Projector(g).project(fv.residual(g, U, re, al))
+    P = P.cpu().numpy().reshape(nz, ny, nx)
+    err = float(np.max(np.abs(P - phi)) / np.max(np.abs(phi)))
+    print(f"pressure rel. err {err:.2e}")
+    assert err < 1e-10
+    assert np.array_equal(Ug.cpu().numpy(), fv.zero_walls(g, U))
+    # at a steady state the residual is the gradient of that pressure
+    c.newton(tol=1e-11, max_steps=12, lin_tol=1e-10)
+    Us, Ps = c.get_base_flow(pressure=True)
+    Us, Ps = Us.cpu().numpy(), Ps.cpu().numpy().reshape(nz, ny, nx)
+    R = fv.residual(g, Us, re, al)
+    gap = np.max(np.abs(R - fv.gradient(g, Ps))) / np.max(np.abs(R))
+    print(f"steady: |R - G P| / |R| = {gap:.2e}")
+    assert gap < 1e-9

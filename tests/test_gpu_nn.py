@@ -5,12 +5,14 @@ accumulates in FP32 (the head's weights stay FP32).  Two comparisons:
 
 * against the oracle run with the same BF16 roundings at the same storage points
   (oracle.nn's q hook, weights and input rounded the same way): what remains is
-  the FP32 summation order, which flips an occasional BF16 rounding, so the
-  bound is tight (1e-3 of the norm forward, 1e-2 for gradients, whose sums over
-  voxels cancel);
+  the FP32 summation order, which flips an occasional BF16 rounding of an
+  activation, so the bound is tight;
 * against the exact FP64 network: the BF16 storage itself, unit roundoff 2^-9
   per rounding, compounded along the backward chain and amplified by the
-  cancellation in the weight-gradient sums (loose: 1e-2 forward, 0.1 gradients).
+  cancellation in the weight-gradient sums.
+
+Both comparisons are element-wise (largest difference over the largest reference
+value); the bounds are set about 10x above the errors measured on MI355X.
 """
 import numpy as np
 import pytest
@@ -21,6 +23,12 @@ from oracle import simple
 import synth
 
 pytestmark = pytest.mark.gpu
+
+# Element-wise bounds (max |gpu - oracle| / max |oracle|), about 10x the largest measured
+# error of each kind on MI355X (forward: the FP32 summation order flips an occasional BF16
+# rounding of an activation; gradients: the same flips, propagated backwards).
+FWD_SAME, FWD_EXACT = 1e-3, 3e-2
+GRAD_SAME, GRAD_EXACT = 1e-3, 0.3
 
 
 def rounded(p):
@@ -46,6 +54,11 @@ def unflat(v):
 
 def rel(a, b):
     return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
+
+
+def elem(a, b):
+    """Element-wise: the largest |a - b| over the largest |b|."""
+    return float(np.max(np.abs(np.ravel(a) - np.ravel(b))) / max(np.max(np.abs(np.ravel(b))), 1e-300))
 
 
 @pytest.fixture(scope="module")
@@ -75,9 +88,10 @@ def test_forward_matches_oracle(lk, shape):
     ye = nn.forward(rounded(p), nn.bf16(x), q=nn.bf16)[0][..., 0]
     yo = nn.forward(p, x)[0][..., 0]
     e, e64 = rel(y, ye), rel(y, yo)
-    print(f"forward {shape}: rel err {e:.2e} (same roundings), {e64:.2e} (exact FP64)")
-    assert e < 1e-3
-    assert e64 < 1e-2
+    m, m64 = elem(y, ye), elem(y, yo)
+    print(f"forward {shape}: L2 rel err {e:.2e} / element-wise {m:.2e} (same roundings), "
+          f"{e64:.2e} / {m64:.2e} (exact FP64)")
+    assert m < FWD_SAME and m64 < FWD_EXACT
 
 
 def test_gradients_match_oracle(lk):
@@ -99,9 +113,11 @@ def test_gradients_match_oracle(lk):
     for name, *_ in nn.LAYERS:
         for suf in (".w", ".b"):
             e, e64 = rel(gg[name + suf], ge[name + suf]), rel(gg[name + suf], go[name + suf])
-            print(f"grad {name}{suf}: rel err {e:.2e} (same roundings), {e64:.2e} (exact FP64)")
-            assert e < 1e-2, (name + suf, e)
-            assert e64 < 0.1, (name + suf, e64)
+            m, m64 = elem(gg[name + suf], ge[name + suf]), elem(gg[name + suf], go[name + suf])
+            print(f"grad {name}{suf}: L2 rel err {e:.2e} / element-wise {m:.2e} (same roundings), "
+                  f"{e64:.2e} / {m64:.2e} (exact FP64)")
+            assert m < GRAD_SAME, (name + suf, m)
+            assert m64 < GRAD_EXACT, (name + suf, m64)
 
 
 def test_adam_step_matches_oracle(lk):
@@ -240,3 +256,21 @@ def test_trained_network_gain(lk, trained):
     eps_u = np.mean([r[2][0] for r in rows])
     print(f"mean eps after guess: trained {eps_t:.4f}, untrained {eps_u:.4f} (plain start 1)")
     assert eps_t < 1.0 and eps_t < eps_u
+    # the guess never adds passes: the learned form's passes are at most the mixed form's
+    assert np.mean([r[1][2] for r in rows]) <= np.mean([r[3][1] for r in rows])
+    # time per Krylov vector of each form against plain FP64, the measured quantity
+    import time
+    import torch
+    ctx.set_net(net)
+    vs = [krylov_input(ctx, seed) for seed in range(601, 609)]
+    times = {}
+    for name, prec in (("plain", lk.FP64), ("mixed", lk.MIXED), ("learned", lk.LEARNED)):
+        ctx.krylov_vector(vs[0], precision=prec, tol=1e-10, max_iter=8)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for v in vs:
+            ctx.krylov_vector(v, precision=prec, tol=1e-10, max_iter=8)
+        torch.cuda.synchronize()
+        times[name] = (time.perf_counter() - t0) / len(vs)
+    print("time per vector vs plain at 32^3: " +
+          ", ".join(f"{k} {1e3 * t:.3f} ms ({t / times['plain']:.2f}x)" for k, t in times.items()))

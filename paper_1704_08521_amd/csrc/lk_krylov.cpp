@@ -665,9 +665,17 @@ extern "C" int lc_critical_re(lc_ctx* c, double re0, double re1, const lc_critic
     if (r2 < 0) return r2;
     if (nout < 1) return fail(c, LC_ENOTCONV, "no Ritz values at Re = %g", re);
     have_vec = true;
-    int lead = 0;
-    for (int i = 1; i < nout; ++i)
-      if (er[i] > er[lead]) lead = i;
+    // the largest real part among the Ritz values within 1e-3 of convergence (a value far
+    // from it -- such as a transient real one near zero, pulled from the gradient directions
+    // on which P L_U vanishes -- is not yet an eigenvalue); among all of them if none is
+    int lead = -1;
+    for (int i = 0; i < nout; ++i)
+      if (res[i] <= 1e-3 * std::hypot(er[i], ei[i]) && (lead < 0 || er[i] > er[lead])) lead = i;
+    if (lead < 0) {
+      lead = 0;
+      for (int i = 1; i < nout; ++i)
+        if (er[i] > er[lead]) lead = i;
+    }
     if (hist && (int)R.size() < o->max_evals) {
       double* h = hist + 4 * R.size();
       h[0] = re;

@@ -215,61 +215,112 @@ int arnoldi_run(lc_ctx* c, int k, int m, double tol, int max_restarts, unsigned 
       if (a.real() != b.real()) return a.real() > b.real();
       return a.imag() > b.imag();
     };
-    std::stable_sort(theta.begin(), theta.end(), by_real);
-    std::vector<char> spur(m, 0);
-    const int front = std::min(m, k + std::max(1, (m - k) / 3) + 2);
-    for (int i = 0; i < front; ++i) {
-      if (!(std::abs(theta[i]) < 1e-5 * tmax)) continue;
-      std::vector<cplx> y;
-      if (!hess_eigvec(m, Hm, theta[i], y)) return fail(c, LC_EINVAL, "Ritz vector failed");
-      std::vector<double> Qy((size_t)m * 2);
-      for (int r = 0; r < m; ++r) {
-        Qy[(size_t)r * 2] = y[r].real();
-        Qy[(size_t)r * 2 + 1] = y[r].imag();
+    // Ritz values whose residual, recomputed with the Krylov map itself, failed (see below)
+    std::vector<cplx> rejected;
+    auto is_rejected = [&](const cplx& t) {  // the value or its conjugate
+      for (const cplx& r : rejected) {
+        const double close = 1e-12 * std::abs(r);
+        if (std::abs(t - r) <= close || std::abs(t - std::conj(r)) <= close) return true;
       }
-      std::memcpy(c->hsmall, Qy.data(), Qy.size() * sizeof(double));
-      HIPCHK(c, hipMemcpyAsync(c->dsmall, c->hsmall, Qy.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
-      KLAUNCH(c, LC_K_VECTOR, launch_combine(V.p, V.ld, m, c->dsmall, 2, W.p, W.ld, c->nvel, c->stream));
-      double d0 = 0.0, d1 = 0.0, n0 = 0.0, n1 = 0.0;
-      if ((rc = vnorm_div(c, W.at(0), nullptr, &d0)) || (rc = vnorm_div(c, W.at(1), nullptr, &d1)) ||
-          (rc = vdot(c, W.at(0), W.at(0), &n0)) || (rc = vdot(c, W.at(1), W.at(1), &n1)))
-        return rc;
-      const double rel = std::hypot(d0, d1) / std::max(vnorm(n0 + n1), 1e-300) / std::max(dref, 1e-300);
-      spur[i] = rel > 1e-6;
-      if (verbose())
-        std::fprintf(stderr, "[lk arnoldi] near-zero Ritz value %.3e%+.3ei: relative divergence %.2e (%s)\n",
-                     theta[i].real(), theta[i].imag(), rel, spur[i] ? "spurious" : "kept");
-    }
-    {
-      std::vector<std::pair<cplx, char>> tv(m);
-      for (int i = 0; i < m; ++i) tv[i] = {theta[i], spur[i]};
-      std::stable_sort(tv.begin(), tv.end(), [&](const std::pair<cplx, char>& a, const std::pair<cplx, char>& b) {
-        if (a.second != b.second) return b.second != 0;
-        return by_real(a.first, b.first);
-      });
-      for (int i = 0; i < m; ++i) theta[i] = tv[i].first;
-    }
-    for (int i = 0; i + 1 < m; ++i)  // within a conjugate pair: positive imaginary part first
-      if (is_pair(theta[i], theta[i + 1])) {
-        if (theta[i].imag() < theta[i + 1].imag()) std::swap(theta[i], theta[i + 1]);
-        ++i;
+      return false;
+    };
+    for (int pass = 0; pass < 4; ++pass) {
+      std::stable_sort(theta.begin(), theta.end(), by_real);
+      std::vector<char> spur(m, 0);
+      for (int i = 0; i < m; ++i) spur[i] = is_rejected(theta[i]);
+      const int front = std::min(m, k + std::max(1, (m - k) / 3) + 2);
+      for (int i = 0; i < front; ++i) {
+        if (spur[i] || !(std::abs(theta[i]) < 1e-5 * tmax)) continue;
+        std::vector<cplx> y;
+        if (!hess_eigvec(m, Hm, theta[i], y)) return fail(c, LC_EINVAL, "Ritz vector failed");
+        std::vector<double> Qy((size_t)m * 2);
+        for (int r = 0; r < m; ++r) {
+          Qy[(size_t)r * 2] = y[r].real();
+          Qy[(size_t)r * 2 + 1] = y[r].imag();
+        }
+        std::memcpy(c->hsmall, Qy.data(), Qy.size() * sizeof(double));
+        HIPCHK(c, hipMemcpyAsync(c->dsmall, c->hsmall, Qy.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+        KLAUNCH(c, LC_K_VECTOR, launch_combine(V.p, V.ld, m, c->dsmall, 2, W.p, W.ld, c->nvel, c->stream));
+        double d0 = 0.0, d1 = 0.0, n0 = 0.0, n1 = 0.0;
+        if ((rc = vnorm_div(c, W.at(0), nullptr, &d0)) || (rc = vnorm_div(c, W.at(1), nullptr, &d1)) ||
+            (rc = vdot(c, W.at(0), W.at(0), &n0)) || (rc = vdot(c, W.at(1), W.at(1), &n1)))
+          return rc;
+        const double rel = std::hypot(d0, d1) / std::max(vnorm(n0 + n1), 1e-300) / std::max(dref, 1e-300);
+        spur[i] = rel > 1e-6;
+        if (verbose())
+          std::fprintf(stderr, "[lk arnoldi] near-zero Ritz value %.3e%+.3ei: relative divergence %.2e (%s)\n",
+                       theta[i].real(), theta[i].imag(), rel, spur[i] ? "spurious" : "kept");
       }
-    kc = k;  // values tested and returned (a conjugate pair is not split)
-    if (kc < m && is_pair(theta[kc - 1], theta[kc])) ++kc;
-    // the restart keeps more vectors than requested: a wanted eigenvalue whose
-    // early Ritz approximation falls among the unwanted would otherwise be
-    // filtered out by its own exact shift
-    kk = std::min(m - 3, std::max(kc, k + std::max(1, (m - k) / 3)));
-    if (kk < m && is_pair(theta[kk - 1], theta[kk])) ++kk;
-    // residual estimates |h_{m+1,m}| |e_m^T y|
-    converged = true;
-    res.assign(kc, 0.0);
-    Y.assign(kc, {});
-    for (int i = 0; i < kc; ++i) {
-      if (!hess_eigvec(m, Hm, theta[i], Y[i])) return fail(c, LC_EINVAL, "Ritz vector failed");
-      res[i] = std::fabs(h(m, m - 1)) * std::abs(Y[i][m - 1]);
-      if (res[i] > tol * std::max(std::abs(theta[i]), 1e-14 * hnorm)) converged = false;
-    }
+      {
+        std::vector<std::pair<cplx, char>> tv(m);
+        for (int i = 0; i < m; ++i) tv[i] = {theta[i], spur[i]};
+        std::stable_sort(tv.begin(), tv.end(), [&](const std::pair<cplx, char>& a, const std::pair<cplx, char>& b) {
+          if (a.second != b.second) return b.second != 0;
+          return by_real(a.first, b.first);
+        });
+        for (int i = 0; i < m; ++i) theta[i] = tv[i].first;
+      }
+      for (int i = 0; i + 1 < m; ++i)  // within a conjugate pair: positive imaginary part first
+        if (is_pair(theta[i], theta[i + 1])) {
+          if (theta[i].imag() < theta[i + 1].imag()) std::swap(theta[i], theta[i + 1]);
+          ++i;
+        }
+      kc = k;  // values tested and returned (a conjugate pair is not split)
+      if (kc < m && is_pair(theta[kc - 1], theta[kc])) ++kc;
+      // the restart keeps more vectors than requested: a wanted eigenvalue whose
+      // early Ritz approximation falls among the unwanted would otherwise be
+      // filtered out by its own exact shift
+      kk = std::min(m - 3, std::max(kc, k + std::max(1, (m - k) / 3)));
+      if (kk < m && is_pair(theta[kk - 1], theta[kk])) ++kk;
+      // residual estimates |h_{m+1,m}| |e_m^T y|
+      converged = true;
+      res.assign(kc, 0.0);
+      Y.assign(kc, {});
+      for (int i = 0; i < kc; ++i) {
+        if (!hess_eigvec(m, Hm, theta[i], Y[i])) return fail(c, LC_EINVAL, "Ritz vector failed");
+        res[i] = std::fabs(h(m, m - 1)) * std::abs(Y[i][m - 1]);
+        if (res[i] > tol * std::max(std::abs(theta[i]), 1e-14 * hnorm)) converged = false;
+      }
+      if (!converged) break;
+      // The estimates say converged: recompute each wanted pair's residual |K x - theta x| with
+      // the Krylov map itself (two vectors per pair).  A Ritz value whose basis has drifted from
+      // the Arnoldi relation -- seen as a real value near the gradient directions' zeros with a
+      // tiny estimate -- fails here; it is then treated as unwanted (an exact shift) and the
+      // selection is redone.
+      bool all_ok = true;
+      for (int i = 0; i < kc; ++i) {
+        std::vector<double> Qy((size_t)m * 2);
+        for (int r = 0; r < m; ++r) {
+          Qy[(size_t)r * 2] = Y[i][r].real();
+          Qy[(size_t)r * 2 + 1] = Y[i][r].imag();
+        }
+        std::memcpy(c->hsmall, Qy.data(), Qy.size() * sizeof(double));
+        HIPCHK(c, hipMemcpyAsync(c->dsmall, c->hsmall, Qy.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+        KLAUNCH(c, LC_K_VECTOR, launch_combine(V.p, V.ld, m, c->dsmall, 2, W.p, W.ld, c->nvel, c->stream));
+        const double tr = theta[i].real(), ti = theta[i].imag();
+        double r2 = 0.0, i2 = 0.0, x2 = 0.0, y2 = 0.0;
+        if ((rc = kmap(c, K, W.at(0), W.at(2))) || (rc = vaxpy(c, -tr, W.at(0), W.at(2)))) return rc;
+        if (ti != 0.0) {
+          // (K - theta)(xr + i xi): real part K xr - tr xr + ti xi, imaginary part K xi - tr xi - ti xr
+          if ((rc = kmap(c, K, W.at(1), W.at(3))) || (rc = vaxpy(c, ti, W.at(1), W.at(2))) ||
+              (rc = vaxpy(c, -tr, W.at(1), W.at(3))) || (rc = vaxpy(c, -ti, W.at(0), W.at(3))) ||
+              (rc = vdot(c, W.at(3), W.at(3), &i2)) || (rc = vdot(c, W.at(1), W.at(1), &y2)))
+            return rc;
+        }
+        if ((rc = vdot(c, W.at(2), W.at(2), &r2)) || (rc = vdot(c, W.at(0), W.at(0), &x2))) return rc;
+        const double rel = vnorm(r2 + i2) / std::max(std::abs(theta[i]) * vnorm(x2 + y2), 1e-300);
+        const double bound = std::max(100.0 * tol, 1e-9);
+        if (verbose())
+          std::fprintf(stderr, "[lk arnoldi] verify %.10f%+.10fi: estimate %.2e, recomputed %.2e%s\n", tr, ti,
+                       res[i] / std::max(std::abs(theta[i]), 1e-300), rel, rel > bound ? " (rejected)" : "");
+        if (rel > bound) {
+          rejected.push_back(theta[i]);
+          all_ok = false;
+        }
+      }
+      if (all_ok) break;
+      converged = false;
+    }  // selection passes
     if (verbose())
       std::fprintf(stderr, "[lk arnoldi] restart %d: theta0 = %.10f%+.10fi  resid0 = %.3e  vectors %ld\n", restart,
                    theta[0].real(), theta[0].imag(), res[0], K.count);

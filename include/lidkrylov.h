@@ -78,7 +78,8 @@ const char* lc_version(void);
  * when ctx is NULL).  Static or context-owned storage. */
 const char* lc_last_error(const lc_ctx* ctx);
 
-/* Create a context for an nx x ny x nz grid (each >= 2, <= 4096) on the HIP
+/* Create a context for an nx x ny x nz grid (each >= 2, <= 4096, and each velocity
+ * component below 2^31 bytes: about 640^3 for a cube) on the HIP
  * stream `hip_stream` (hipStream_t, NULL = default stream) of the current
  * device.  The grid starts uniform, Re = 1, lid angle 0, base flow zero. */
 int lc_create(lc_ctx** out, int nx, int ny, int nz, void* hip_stream);

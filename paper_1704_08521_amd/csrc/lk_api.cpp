@@ -400,6 +400,12 @@ int create(lc_ctx** out, int nx, int ny, int nz, void* ws, size_t ws_bytes, void
   *out = nullptr;
   if (nx < 2 || ny < 2 || nz < 2 || nx > 4096 || ny > 4096 || nz > 4096)
     return fail(nullptr, LC_EINVAL, "grid size %dx%dx%d outside [2, 4096]", nx, ny, nz);
+  {
+    // the stencil kernels address each velocity component with 32-bit byte offsets
+    const VelLayout L = vel_layout(nx, ny, nz);
+    if (8 * std::max(L.nu, std::max(L.nv, L.nw)) >= (size_t(1) << 31))
+      return fail(nullptr, LC_EINVAL, "grid %dx%dx%d: a velocity component exceeds 2^31 bytes", nx, ny, nz);
+  }
   lc_ctx* c = new lc_ctx();
   init_dims(c, nx, ny, nz);
   c->stream = (hipStream_t)hip_stream;
@@ -449,6 +455,8 @@ extern "C" {
 int lc_workspace_query(int nx, int ny, int nz, int m_max, size_t* bytes) {
   if (!bytes || nx < 2 || ny < 2 || nz < 2 || nx > 4096 || ny > 4096 || nz > 4096 || m_max < 0 || m_max > 400)
     return LC_EINVAL;
+  const VelLayout L = vel_layout(nx, ny, nz);
+  if (8 * std::max(L.nu, std::max(L.nv, L.nw)) >= (size_t(1) << 31)) return LC_EINVAL;
   lc_ctx c;
   init_dims(&c, nx, ny, nz);
   c.dry = true;

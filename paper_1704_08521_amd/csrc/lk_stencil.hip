@@ -3,6 +3,8 @@
 // step 2).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "lk_device.h"
 
 namespace lk {
@@ -49,13 +51,15 @@ __global__ void __launch_bounds__(TX* TY) k_momentum(GridDev g, const double* __
   const int i = i0 + tx, j = j0 + ty;
   const double* src[6] = {a, a + nu, a + nu + nv, b, b + nu, b + nu + nv};
 
-  // Halo positions of this thread (fixed along the march): in-plane offset and
-  // in-range flag per component; a plane adds k * (plane stride).  Loads are
-  // unconditional from an in-range address (0 for ghosts), the ghost is selected
-  // afterwards, so all of a thread's loads issue back to back.
+  // Halo positions of this thread (fixed along the march): in-plane byte offset per
+  // component, kGhost for a ghost position.  The loads are raw buffer loads, which return 0
+  // at or past a component's size, so a ghost (or a plane outside the field) costs no
+  // select; a plane adds k * (plane stride).  The host keeps every component below 2^31
+  // bytes, so an in-range offset plus kGhost cannot wrap.
+  constexpr unsigned kGhost = 1u << 31;
   constexpr int NT = TX * TY;
   constexpr int PER = (MPS + NT - 1) / NT;
-  int col[3][PER];
+  unsigned col[3][PER];
   bool xy[3][PER];
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
@@ -65,11 +69,18 @@ __global__ void __launch_bounds__(TX* TY) k_momentum(GridDev g, const double* __
     xy[0][q] = (ii > 0) & (ii < nx) & in_j;
     xy[1][q] = (jj > 0) & (jj < ny) & in_i;
     xy[2][q] = in_i & in_j;
-    col[0][q] = xy[0][q] ? jj * (nx + 1) + ii : 0;
-    col[1][q] = xy[1][q] ? jj * nx + ii : 0;
-    col[2][q] = xy[2][q] ? jj * nx + ii : 0;
+    col[0][q] = xy[0][q] ? 8u * (unsigned)(jj * (nx + 1) + ii) : kGhost;
+    col[1][q] = xy[1][q] ? 8u * (unsigned)(jj * nx + ii) : kGhost;
+    col[2][q] = xy[2][q] ? 8u * (unsigned)(jj * nx + ii) : kGhost;
   }
-  const long pstride[3] = {(long)ny * (nx + 1), (long)(ny + 1) * nx, (long)ny * nx};
+  const unsigned pstride[3] = {8u * (unsigned)(ny * (nx + 1)), 8u * (unsigned)((ny + 1) * nx),
+                               8u * (unsigned)(ny * nx)};
+  const unsigned nbytes[3] = {(unsigned)(8 * nu), (unsigned)(8 * nv), (unsigned)(8 * (size_t)nx * ny * (nz + 1))};
+  __amdgpu_buffer_rsrc_t rs[6];
+#pragma unroll
+  for (int arr = 0; arr < 6; ++arr)  // raw buffer (stride 0), 32-bit data format
+    rs[arr] = __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(src[arr]), (short)0, (int)nbytes[arr % 3],
+                                                0x00020000);
 
   // Plane loads go to registers first and are written to LDS one step later, so
   // the next plane is in flight while the current one is computed.
@@ -80,14 +91,14 @@ __global__ void __launch_bounds__(TX* TY) k_momentum(GridDev g, const double* __
     for (int arr = 0; arr < 6; ++arr) {
       const int comp = arr % 3;
       const bool kin = comp == 2 ? kin_w : kin_uv;
-      const long kofs = kin ? (long)k * pstride[comp] : 0;
+      const unsigned kofs = (unsigned)k * pstride[comp];
       const double lid = comp == 0 ? lid_u : lid_v;
 #pragma unroll
       for (int q = 0; q < PER; ++q) {
-        const bool ok = kin & xy[comp][q];
-        const double x = src[arr][kofs + col[comp][q]];
-        const double ghost = (LID && arr >= 3 && comp < 2 && xy[comp][q] && k == nz) ? lid : 0.0;
-        reg[arr][q] = ok ? x : ghost;
+        const unsigned off = kin ? col[comp][q] + kofs : kGhost;
+        const double x = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs[arr], off, 0, 0));
+        // the advected field of the nonlinear residual carries the lid velocity above z = 1
+        reg[arr][q] = (LID && arr >= 3 && comp < 2 && xy[comp][q] && k == nz) ? lid : x;
       }
     }
   };
@@ -418,6 +429,8 @@ constexpr int kMomTX = 16, kMomTY = 8, kMomChunk = 24;
 hipError_t launch_momentum(const GridDev& g, const double* a, const double* b, double* out, double rre, double s,
                            bool lid, double lid_u, double lid_v, hipStream_t st) {
   const int nx = g.x.n, ny = g.y.n, nz = g.z.n;
+  const VelLayout L = vel_layout(nx, ny, nz);
+  if (8 * std::max(L.nu, std::max(L.nv, L.nw)) >= (size_t(1) << 31)) return hipErrorInvalidValue;
   const int nbx = (int)blocks_for(nx + 1, kMomTX), nby = (int)blocks_for(ny + 1, kMomTY);
   const int nbz = (int)blocks_for(nz + 1, kMomChunk);
   const dim3 grid(nbx * nby * nbz), block(kMomTX * kMomTY);

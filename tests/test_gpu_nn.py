@@ -12,7 +12,8 @@ accumulates in FP32 (the head's weights stay FP32).  Two comparisons:
   cancellation in the weight-gradient sums.
 
 Both comparisons are element-wise (largest difference over the largest reference
-value); the bounds are set about 10x above the errors measured on MI355X.
+value); each bound sits between 1x and 10x above the largest error of its kind measured on
+MI355X (see the constants below).
 """
 import numpy as np
 import pytest
@@ -24,11 +25,13 @@ import synth
 
 pytestmark = pytest.mark.gpu
 
-# Element-wise bounds (max |gpu - oracle| / max |oracle|), about 10x the largest measured
-# error of each kind on MI355X (forward: the FP32 summation order flips an occasional BF16
-# rounding of an activation; gradients: the same flips, propagated backwards).
+# Element-wise bounds (max |gpu - oracle| / max |oracle|).  Largest errors measured on
+# MI355X over the cases below: forward 3.9e-4 with the same roundings (the FP32 summation
+# order flips an occasional BF16 rounding of an activation; 6e-8 where none flips) and
+# 4.0e-3 against FP64; gradients 2.0e-7 with the same roundings and 0.23 against FP64 (the
+# BF16 storage compounded along the backward chain, worst in the bottleneck weights).
 FWD_SAME, FWD_EXACT = 1e-3, 3e-2
-GRAD_SAME, GRAD_EXACT = 1e-3, 0.3
+GRAD_SAME, GRAD_EXACT = 2e-6, 0.3
 
 
 def rounded(p):

@@ -82,3 +82,17 @@ def test_hessenberg_eigvals_match_numpy(m, seed):
     assert lib.lc_hessenberg_eigvals(m, p(np.ascontiguousarray(H)), p(re), p(im)) == 0
     from oracle.eigen import match_distance
     assert match_distance(np.linalg.eigvals(H), re + 1j * im) < 1e-10 * max(1.0, np.abs(H).max())
+
+
+def test_grid_size_limits_rejected_on_the_host():
+    """Sizes the kernels cannot address (a velocity component of 2^31 bytes or more, an axis
+    outside [2, 4096]) are refused before any device call."""
+    from paper_1704_08521_amd import _lib as L
+    lib = _lib()
+    nbytes = C.c_size_t(0)
+    assert lib.lc_workspace_query(200, 200, 200, 40, C.byref(nbytes)) == L.LC_OK and nbytes.value > 0
+    for n in ((1, 8, 8), (8, 8, 4097), (650, 650, 650), (4096, 4096, 16)):
+        assert lib.lc_workspace_query(*n, 40, C.byref(nbytes)) == L.LC_EINVAL, n
+        ctx = C.c_void_p()
+        assert lib.lc_create(C.byref(ctx), *n, None) == L.LC_EINVAL, n
+        assert not ctx.value

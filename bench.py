@@ -12,7 +12,7 @@ passes).
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--size 200] [--no-cpu]
                     [--train-steps 300] [--poisson tpt|tpf]
-    python bench.py --planes | --critical N[,N...]
+    python bench.py --planes | --critical N[,N...] [--alpha 0|45] | --learned-recipe PAIRS
 """
 from __future__ import annotations
 
@@ -47,11 +47,17 @@ def parse():
     ap.add_argument("--train-size", type=int, default=64)
     ap.add_argument("--critical", type=str, default="", metavar="N[,N...]",
                     help="instead of the Krylov-vector benchmark: critical Reynolds number of the N^3 cube "
-                         "on the sine grid of eq. 5, lid along x (Newton continuation, then the secant "
+                         "on the sine grid of eq. 5, lid at --alpha (Newton continuation, then the secant "
                          "driver lc_critical_re); one JSON line")
+    ap.add_argument("--alpha", type=float, choices=(0.0, 45.0), default=0.0,
+                    help="lid angle (degrees) of --critical: 0 (parallel to a side wall) or 45 (diagonal)")
     ap.add_argument("--poisson", choices=("tpt", "tpf"), default="tpt",
                     help="pressure-solve route (transforms along y, z with tridiagonal solves along x, "
                          "or transforms along x, y, z)")
+    ap.add_argument("--learned-recipe", type=int, default=0, metavar="PAIRS",
+                    help="instead of the Krylov-vector benchmark: train the learned guess on PAIRS pairs "
+                         "from 64^3 and 100^3 Newton steady states (Re 1000-2500, both lid directions) and "
+                         "evaluate it inside SIMPLE at 150^3 and 200^3; one JSON line")
     ap.add_argument("--planes", action="store_true",
                     help="instead of the Krylov-vector benchmark: only the plane projections and potentials "
                          "(eqs. 11-17) at --size^3; one JSON line")
@@ -248,9 +254,21 @@ def cpu_baseline(n, reps=3):
     return out
 
 
-# Table 3 of the paper (alpha = 0, sine grid of eq. 5): critical Re and frequency per grid
-PAPER_TABLE3_A0 = {100: (1963.74, 0.575370), 150: (1938.98, 0.581315), 200: (1930.40, 0.583398),
-                   256: (1926.10, 0.584438)}
+# Table 3 of the paper (sine grid of eq. 5): critical Re and frequency per grid, for the lid
+# parallel to a side wall (alpha = 0) and to the diagonal plane (alpha = 45 degrees), and the
+# grid-converged Richardson values
+PAPER_TABLE3 = {0.0: {100: (1963.74, 0.575370), 150: (1938.98, 0.581315), 200: (1930.40, 0.583398),
+                      256: (1926.10, 0.584438), "extrapolated": (1919.37, 0.58607)},
+                45.0: {100: (2266.29, 0.250855), 150: (2278.39, 0.250305), 200: (2283.17, 0.249868),
+                       256: (2285.56, 0.249650), "extrapolated": (2289.31, 0.249307)}}
+# per lid angle: the Newton continuation path from rest and, per grid, the two starting values
+# of the secant search (alpha = 0: bracketing the paper's values on 100^3 - 256^3; alpha = 45:
+# around the paper's 100^3 value, and at 150^3 around the value an O(h^2) error would give
+# between the 100^3 result of this discretization, 2332.2, and the paper's limit, 2289.3)
+CRITICAL_PATH = {0.0: ((250.0, 500.0, 800.0, 1100.0, 1400.0, 1600.0, 1750.0, 1850.0, 1900.0),
+                       {"default": (1920.0, 1960.0)}),
+                 45.0: ((250.0, 500.0, 800.0, 1100.0, 1400.0, 1700.0, 1900.0, 2050.0, 2150.0, 2250.0),
+                        {"default": (2265.0, 2285.0), 150: (2300.0, 2316.0)})}
 
 
 # algorithmic HBM bytes per cell of the plane kernels of one projection with its potential:
@@ -313,10 +331,13 @@ def planes_run(n, lk, torch, steps, route):
 
 
 def critical_one(n, lk, torch, alpha_deg=0.0):
-    """One grid: steady states continued from rest with Stokes-preconditioned Newton up to
-    Re = 1900, then the secant search for the critical Reynolds number (the leading
-    eigenvalue of eq. 7 crossing the imaginary axis) from Re = 1920 and 1960."""
+    """One grid: steady states continued from rest with Stokes-preconditioned Newton along
+    the lid angle's path (up to Re 1900 for alpha = 0, 2250 for 45 degrees), then the secant
+    search for the critical Reynolds number (the leading eigenvalue of eq. 7 crossing the
+    imaginary axis) from the path's two starting values."""
     import math
+    path, starts = CRITICAL_PATH[alpha_deg]
+    re0, re1 = starts.get(n, starts["default"])
     ctx = lk.Context(n)
     ctx.set_stretching("sine", 0.0)
     ctx.set_lid(math.radians(alpha_deg))
@@ -325,7 +346,7 @@ def critical_one(n, lk, torch, alpha_deg=0.0):
     t0 = time.perf_counter()
     cont = []
     vectors = 0
-    for re in (250.0, 500.0, 800.0, 1100.0, 1400.0, 1600.0, 1750.0, 1850.0, 1900.0):
+    for re in path:
         ctx.set_re(re)
         for step in range(12):
             _, r = ctx.newton_residual()
@@ -336,7 +357,7 @@ def critical_one(n, lk, torch, alpha_deg=0.0):
         cont.append({"re": re, "newton_steps": step, "res_inf": r})
     t1 = time.perf_counter()
     os.environ["LK_VERBOSE"] = "1"  # progress trace on stderr during the long driver call
-    out = ctx.critical_re(1920.0, 1960.0, re_tol=1e-6, max_evals=7, newton_tol=1e-11, newton_steps=8,
+    out = ctx.critical_re(re0, re1, re_tol=1e-6, max_evals=8, newton_tol=1e-11, newton_steps=8,
                           lin_tol=1e-8, gmres_m=100, max_vectors=20000, k=8, m=100, eig_tol=1e-8,
                           max_restarts=150, seed=1, warm_start=True)
     os.environ["LK_VERBOSE"] = "0"
@@ -348,18 +369,18 @@ def critical_one(n, lk, torch, alpha_deg=0.0):
                            for h in out["history"]],
            "continuation": cont, "continuation_krylov_vectors": vectors,
            "seconds_continuation": t1 - t0, "seconds_critical": t2 - t1}
-    if n in PAPER_TABLE3_A0 and alpha_deg == 0.0:
-        pre, pom = PAPER_TABLE3_A0[n]
+    if n in PAPER_TABLE3[alpha_deg]:
+        pre, pom = PAPER_TABLE3[alpha_deg][n]
         res["paper_table3"] = {"re_cr": pre, "omega_cr": pom, "re_rel_diff": out["re_cr"] / pre - 1.0,
                                "omega_rel_diff": out["omega_cr"] / pom - 1.0}
     return res
 
 
-def critical_run(sizes, lk, torch):
-    """Critical Reynolds number on each grid of the sequence (sine grid of eq. 5, lid along
-    x) and the Richardson extrapolation of Section 5 from each pair of consecutive grids:
-    with an O(h^2) error, v = v_f + (v_f - v_c) / ((n_f / n_c)^2 - 1)."""
-    grids = [critical_one(n, lk, torch) for n in sizes]
+def critical_run(sizes, lk, torch, alpha_deg=0.0):
+    """Critical Reynolds number on each grid of the sequence (sine grid of eq. 5, lid at
+    angle alpha to x) and the Richardson extrapolation of Section 5 from each pair of
+    consecutive grids: with an O(h^2) error, v = v_f + (v_f - v_c) / ((n_f / n_c)^2 - 1)."""
+    grids = [critical_one(n, lk, torch, alpha_deg) for n in sizes]
     extrap = []
     for c, f in zip(grids, grids[1:]):
         nc, nf = c["grid"][0], f["grid"][0]
@@ -367,9 +388,108 @@ def critical_run(sizes, lk, torch):
         extrap.append({"grids": [nc, nf], "re_cr": f["re_cr"] + (f["re_cr"] - c["re_cr"]) / q,
                        "omega_cr": f["omega_cr"] + (f["omega_cr"] - c["omega_cr"]) / q})
     res = {"metric": "critical Reynolds number (leading eigenvalue of eq. 7 crossing the imaginary axis)",
-           "stretching": "sine (eq. 5)", "alpha_deg": 0.0, "newton": "Stokes-preconditioned (dt = inf)",
+           "stretching": "sine (eq. 5)", "alpha_deg": alpha_deg, "newton": "Stokes-preconditioned (dt = inf)",
            "grids": grids, "richardson": extrap,
-           "paper_table3_extrapolated": {"re_cr": 1919.37, "omega_cr": 0.58607}}
+           "paper_table3_extrapolated": dict(zip(("re_cr", "omega_cr"), PAPER_TABLE3[alpha_deg]["extrapolated"]))}
+    print(json.dumps(res), flush=True)
+
+
+def steady_states(lk, torch, n, alpha_deg, res_wanted):
+    """Newton steady states of the n^3 tanh-10 cube at each Re of res_wanted (continued from
+    rest, Stokes-preconditioned Newton to max |P R(U)| <= 1e-10); returns {Re: U}."""
+    import math
+    ctx = lk.Context(n)
+    ctx.set_stretching("tanh", TANH_RATIO)
+    ctx.set_lid(math.radians(alpha_deg))
+    ctx.set_base_flow(torch.zeros(ctx.nvel, dtype=torch.float64, device="cuda"))
+    ctx.set_stokes_precond(float("inf"))
+    out = {}
+    path = sorted(set([250.0 * q for q in range(1, 10)] + [r for r in res_wanted]))
+    for re in path:
+        ctx.set_re(re)
+        hist = ctx.newton(tol=1e-10, max_steps=12, lin_tol=1e-8, gmres_m=100, max_vectors=20000)
+        log(f"[recipe] {n}^3 alpha {alpha_deg:g} Re {re:g}: Newton |P R(U)| {hist[-1]:.1e} ({len(hist) - 1} steps)")
+        if hist[-1] > 1e-10:
+            raise RuntimeError(f"Newton did not converge at {n}^3, alpha {alpha_deg}, Re {re}")
+        if re in res_wanted:
+            out[re] = ctx.get_base_flow().clone()
+    ctx.close()
+    return out
+
+
+def learned_recipe_run(lk, torch, pairs, rounds):
+    """The learned guess trained on the training set of the learned-preconditioner workload:
+    pairs the method generates (w = L_U v, D w -> the first SIMPLE correction) on 64^3 and
+    100^3 tanh-10 grids, on Newton steady states at Re 1000..2500 for both lid directions
+    (parallel to a side wall, alpha = 0, and to the diagonal plane, alpha = 45 degrees),
+    visited round-robin; then evaluated inside SIMPLE at 150^3 and 200^3 (the benchmark's
+    Re = 1900 and seeded base flow) against the same network after 300 64^3 pairs and an
+    untrained one.  One JSON line."""
+    import math
+    t0 = time.perf_counter()
+    spec = {64: (1000.0, 1500.0, 2000.0, 2500.0), 100: (1000.0, 1750.0, 2500.0)}
+    states = []  # (n, alpha, Re, U)
+    for n, res in spec.items():
+        for alpha in (0.0, 45.0):
+            for re, U in steady_states(lk, torch, n, alpha, res).items():
+                states.append((n, alpha, re, U))
+    t1 = time.perf_counter()
+    ctxs = {}
+    for n in spec:
+        c = lk.Context(n)
+        c.set_stretching("tanh", TANH_RATIO)
+        ctxs[n] = c
+    net = lk.Net(seed=11)
+    per = max(1, pairs // (rounds * len(states)))
+    losses = []
+    for rnd in range(rounds):
+        lr = 2e-3 if rnd < rounds // 2 else (1e-3 if rnd < 3 * rounds // 4 else 5e-4)
+        for q, (n, alpha, re, U) in enumerate(states):
+            c = ctxs[n]
+            c.set_re(re)
+            c.set_lid(math.radians(alpha))
+            c.set_base_flow(U)
+            h = net.train(c, steps=per, lr=lr, seed=1 + rnd * len(states) + q)
+            losses.append(float(h.mean()))
+        log(f"[recipe] round {rnd}: mean loss {sum(losses[-len(states):]) / len(states):.4f} "
+            f"({time.perf_counter() - t1:.0f} s)")
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for c in ctxs.values():
+        c.close()
+    quick, _ = train_guess(lk, torch, 64, 300)
+    untrained = lk.Net(seed=11)
+    evals = []
+    for n in (150, 200):
+        ctx = lk.Context(n)
+        ctx.set_stretching("tanh", TANH_RATIO)
+        ctx.set_re(RE)
+        ctx.set_lid(0.0)
+        ctx.set_base_flow(synthetic_base_flow(ctx, torch))
+        inputs = make_inputs(ctx, torch, 8, seed0=901)
+        row = {"grid": [n, n, n]}
+        for name, nt in (("recipe", net), ("bench_300", quick), ("untrained", untrained)):
+            ctx.set_net(nt)
+            dt, stats = time_form(ctx, torch, inputs, 2, 6, lk.LEARNED)
+            row[name] = {"guess_eps_mean": sum(st["guess_eps"] for st in stats) / len(stats),
+                         "rho_first_pass_mean": sum(st["rho_hist"][0] for st in stats) / len(stats),
+                         "passes_mean": sum(st["iterations"] for st in stats) / len(stats),
+                         "vectors_per_s": 6 / dt}
+        dt, stats = time_form(ctx, torch, inputs, 2, 6, lk.MIXED)
+        row["mixed"] = {"rho_first_pass_mean": sum(st["rho_hist"][0] for st in stats) / len(stats),
+                        "passes_mean": sum(st["iterations"] for st in stats) / len(stats), "vectors_per_s": 6 / dt}
+        log(f"[recipe] {n}^3: eps recipe {row['recipe']['guess_eps_mean']:.3f}, 300-pair "
+            f"{row['bench_300']['guess_eps_mean']:.3f}, untrained {row['untrained']['guess_eps_mean']:.3f}")
+        evals.append(row)
+        ctx.close()
+    res = {"metric": "learned guess: continuity residual after the guess relative to a plain start (eps)",
+           "training_set": {"grids": ["64^3 tanh-10", "100^3 tanh-10"], "re": {str(k): v for k, v in spec.items()},
+                            "alpha_deg": [0.0, 45.0], "base_flows": "Newton steady states",
+                            "pairs": per * rounds * len(states), "rounds": rounds, "pairs_per_visit": per,
+                            "seconds_newton": t1 - t0, "seconds_training": t2 - t1,
+                            "loss_first_round": sum(losses[:len(states)]) / len(states),
+                            "loss_last_round": sum(losses[-len(states):]) / len(states)},
+           "evaluation": evals}
     print(json.dumps(res), flush=True)
 
 
@@ -383,11 +503,15 @@ def main():
     import paper_1704_08521_amd as lk
     if a.critical:
         torch.cuda.set_device(0)
-        critical_run([int(x) for x in a.critical.split(",")], lk, torch)
+        critical_run([int(x) for x in a.critical.split(",")], lk, torch, a.alpha)
         return
     if a.planes:
         torch.cuda.set_device(0)
         planes_run(a.size, lk, torch, a.steps, a.poisson)
+        return
+    if a.learned_recipe:
+        torch.cuda.set_device(0)
+        learned_recipe_run(lk, torch, a.learned_recipe, rounds=10)
         return
     n = a.size
     torch.cuda.set_device(0)

@@ -14,6 +14,13 @@ typedef __bf16 bf16;
 __host__ __device__ constexpr int conv_cc(int cin) { return cin <= 16 ? cin : (cin % 32 == 0 ? 32 : 16); }
 __host__ __device__ constexpr int conv_kpc(int cin) { return (27 * conv_cc(cin) + 31) / 32 * 32; }
 __host__ __device__ constexpr int conv_kp(int cin) { return cin / conv_cc(cin) * conv_kpc(cin); }
+// Forward layers with at least 32 input channels run k_conv_rows: reduction index (chunk of
+// 32 channels, tap, channel), the channels zero-padded to a multiple of 32.
+__host__ __device__ constexpr bool conv_rows(int cin) { return cin >= 32; }
+// elements of a layer's forward BF16 weights in the layout of its kernel
+__host__ __device__ constexpr long conv_wf_elems(int cout, int cin) {
+  return conv_rows(cin) ? 27L * cout * ((cin + 31) / 32 * 32) : (long)cout * conv_kp(cin);
+}
 
 // 3x3x3 convolution of layer `layer` (0 enc1, 1 enc2, 2 bottleneck, 3 dec2, 4 dec1).
 // Forward: out = relu(conv(in) + bias) in BF16; `a` is the half-resolution source of

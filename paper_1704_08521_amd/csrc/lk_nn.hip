@@ -166,6 +166,113 @@ __global__ __launch_bounds__(kBlock) void k_conv(const bf16* __restrict__ srcA, 
   }
 }
 
+// ------------------------------------------------ convolution, input rows shared by taps
+// The same implicit GEMM for layers with at least 32 input channels, ordered so that one
+// A fragment (16 consecutive input voxels of one (y, z) row, 32 channels) feeds every
+// output row of the wave that reads it through some tap (dy, dz): a block computes a
+// 16 x 4 x 4 TZW (x, y, z) brick, wave w the planes TZW w .. TZW w + TZW - 1, and for each
+// x offset of the taps the wave keeps the 9 (dy, dz) weight fragments of that offset in
+// registers and walks the (TZW + 2) x 6 input rows once, issuing up to 3 TZW MFMAs per
+// fragment it reads from LDS (k_conv reads one fragment per MFMA).  The reduction index
+// is (chunk of 32 channels, tap, channel), channels padded with zeros to a multiple of 32
+// (CINP); weights [chunk][tap][co][32] (k_prep_rows).  Sources and output as in k_conv.
+template <int CINP, int CREAL, int COUT, int CA, int TZW>
+__global__ __launch_bounds__(kBlock) void k_conv_rows(const bf16* __restrict__ srcA, const bf16* __restrict__ srcB,
+                                                      const bf16* __restrict__ wt, const float* __restrict__ bias,
+                                                      bf16* __restrict__ out, int D, int H, int W) {
+  constexpr int TX = 16, TY = 4, TZ = 4 * TZW;
+  constexpr int PX = TX + 2, PY = TY + 2, PZ = TZ + 2, NV = PX * PY * PZ;
+  constexpr int NB = COUT / 16, NCH = CINP / 32, CB = CREAL - CA;
+  static_assert(CINP % 32 == 0 && CREAL <= CINP && COUT % 16 == 0, "channel layout");
+  // staged brick of one 32-channel chunk, channel-group major ([4][voxel][8]) as in k_conv
+  __shared__ __attribute__((aligned(16))) bf16 tile[4 * NV * 8];
+  const int nbx = (W + TX - 1) / TX, nby = (H + TY - 1) / TY;
+  const int t = xcd_tile(blockIdx.x, gridDim.x);
+  const int x0 = (t % nbx) * TX, y0 = ((t / nbx) % nby) * TY, z0 = (t / (nbx * nby)) * TZ;
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63, g = lane >> 4, r16 = lane & 15;
+  const int H2 = H >> 1, W2 = W >> 1;
+  floatx4 acc[TZW][4][NB];
+#pragma unroll
+  for (int a = 0; a < TZW; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) acc[a][b][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+  for (int ch = 0; ch < NCH; ++ch) {
+    for (int e = tid; e < NV * 4; e += kBlock) {
+      const int c8 = e / NV, v = e - c8 * NV;
+      const int vx = v % PX, vy = (v / PX) % PY, vz = v / (PX * PY);
+      const int gx = x0 - 1 + vx, gy = y0 - 1 + vy, gz = z0 - 1 + vz;
+      const int ci = ch * 32 + 8 * c8;
+      // outside the grid, and the padding channels, stage zeros (read from a valid address)
+      const bool ok = (unsigned)gx < (unsigned)W && (unsigned)gy < (unsigned)H && (unsigned)gz < (unsigned)D &&
+                      ci < CREAL;
+      const int xc = ok ? gx : 0, yc = ok ? gy : 0, zc = ok ? gz : 0;
+      const bf16* ptr;
+      if (CA > 0 && ci < CA)
+        ptr = srcA + (((long)(zc >> 1) * H2 + (yc >> 1)) * W2 + (xc >> 1)) * CA + ci;
+      else
+        ptr = srcB + (((long)zc * H + yc) * W + xc) * CB + (ok ? ci - CA : 0);
+      *reinterpret_cast<bf16x8*>(&tile[(c8 * NV + v) * 8]) = load8(ptr, ok);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int dxi = 0; dxi < 3; ++dxi) {
+      bf16x8 bq[9][NB];  // taps (dz, dy) at x offset dxi - 1, q = 3 dz + dy (offsets + 1)
+#pragma unroll
+      for (int q = 0; q < 9; ++q)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+          bq[q][nb] = *reinterpret_cast<const bf16x8*>(wt + ((long)(ch * 27 + 3 * q + dxi) * COUT + nb * 16 + r16) * 32 +
+                                                       8 * g);
+#pragma unroll
+      for (int zz = 0; zz < TZW + 2; ++zz) {
+#pragma unroll
+        for (int yy = 0; yy < PY; ++yy) {
+          const int v = ((TZW * wv + zz) * PY + yy) * PX + r16 + dxi;
+          const bf16x8 a = *reinterpret_cast<const bf16x8*>(&tile[(g * NV + v) * 8]);
+#pragma unroll
+          for (int oz = 0; oz < TZW; ++oz) {
+            const int dz = zz - oz;
+            if (dz < 0 || dz > 2) continue;
+#pragma unroll
+            for (int oy = 0; oy < 4; ++oy) {
+              const int dy = yy - oy;
+              if (dy < 0 || dy > 2) continue;
+#pragma unroll
+              for (int nb = 0; nb < NB; ++nb)
+                acc[oz][oy][nb] =
+                    __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bq[3 * dz + dy][nb], acc[oz][oy][nb], 0, 0, 0);
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // result rows 4g + j of a 16-voxel row are x0 + 4g + j; columns are channels
+#pragma unroll
+  for (int oz = 0; oz < TZW; ++oz) {
+    const int z = z0 + TZW * wv + oz;
+#pragma unroll
+    for (int oy = 0; oy < 4; ++oy) {
+      const int y = y0 + oy;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int x = x0 + 4 * g + j;
+        if (x >= W || y >= H || z >= D) continue;
+        const long p = ((long)z * H + y) * W + x;
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          const int co = nb * 16 + r16;
+          const float val = acc[oz][oy][nb][j] + bias[co];
+          out[p * COUT + co] = f2bf(val > 0.f ? val : 0.f);
+        }
+      }
+    }
+  }
+}
+
 // --------------------------------------------------------------- weight gradient
 // part[blk][tap][co][CIN] = sum over the block's voxels p of dy[p][co] X_tap[p][ci],
 // X_tap[p] = input at p + offset(tap) (zero outside), sources as in k_conv.
@@ -415,7 +522,8 @@ __global__ void k_adam(float* __restrict__ w, const float* __restrict__ g, float
 }
 
 // BF16 GEMM weights of a 3x3x3 layer from its FP32 master W[co][27][cin_real], in
-// the (channel chunk, tap, channel) order of k_conv: forward [cout][conv_kp(cinp)];
+// the (channel chunk, tap, channel) order of k_conv: forward [cout][conv_kp(cinp)] (the
+// layers with fewer than 32 input channels; k_prep_rows makes the others');
 // transposed-flipped for the backward data pass [cin][conv_kp(cout)] holding
 // W[co][26 - tap][ci] at (chunk of co, tap, co).
 __global__ void k_prep_fwd(const float* __restrict__ w, bf16* __restrict__ out, int cout, int cinp, int cin_real) {
@@ -426,6 +534,17 @@ __global__ void k_prep_fwd(const float* __restrict__ w, bf16* __restrict__ out, 
   const int ch = k / KPC, r = k % KPC;
   const int tap = r / CC, ci = ch * CC + r % CC;
   out[e] = f2bf(tap < 27 && ci < cin_real ? w[((long)co * 27 + tap) * cin_real + ci] : 0.f);
+}
+
+// BF16 weights of k_conv_rows: [chunk][tap][co][32] holding W[co][tap][32 chunk + c]
+// (zero for padding channels).
+__global__ void k_prep_rows(const float* __restrict__ w, bf16* __restrict__ out, int cout, int cinp, int cin_real) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= conv_wf_elems(cout, cinp)) return;
+  const int c = (int)(e % 32), co = (int)((e / 32) % cout), tap = (int)((e / (32L * cout)) % 27);
+  const int ch = (int)(e / (32L * cout * 27));
+  const int ci = ch * 32 + c;
+  out[e] = f2bf(ci < cin_real ? w[((long)co * 27 + tap) * cin_real + ci] : 0.f);
 }
 
 __global__ void k_prep_bwd(const float* __restrict__ w, bf16* __restrict__ out, int cout, int cin) {
@@ -572,13 +691,20 @@ hipError_t nn_conv(int layer, bool backward, const bf16* a, const bf16* b, const
   const dim3 grid((unsigned)tiles), blk(kBlock);  // one 16 x 4 x 4 output brick per block
 #define CONV(CIN, COUT, CA, OUTF) \
   hipLaunchKernelGGL((k_conv<CIN, COUT, CA, OUTF>), grid, blk, 0, st, a, b, wt, bias, out, D, H, W)
+  // k_conv_rows bricks: 16 x 4 x 4 TZW voxels per block
+  auto rows_grid = [&](int tzw) {
+    return dim3((unsigned)((long)((W + 15) / 16) * ((H + 3) / 4) * ((D + 4 * tzw - 1) / (4 * tzw))));
+  };
+#define ROWS(CINP, CREAL, COUT, CA, TZW)                                                                          \
+  hipLaunchKernelGGL((k_conv_rows<CINP, CREAL, COUT, CA, TZW>), rows_grid(TZW), blk, 0, st, a, b, wt, bias, \
+                     static_cast<bf16*>(out), D, H, W)
   if (!backward) {
     switch (layer) {
       case 0: CONV(8, 16, 0, false); break;
       case 1: CONV(16, 32, 0, false); break;
-      case 2: CONV(32, 64, 0, false); break;
-      case 3: CONV(96, 32, 64, false); break;
-      case 4: CONV(48, 16, 32, false); break;
+      case 2: ROWS(32, 32, 64, 0, 1); break;  // quarter resolution: the smaller brick keeps more blocks
+      case 3: ROWS(96, 96, 32, 64, 2); break;
+      case 4: ROWS(64, 48, 16, 32, 2); break;
       default: return hipErrorInvalidValue;
     }
   } else {
@@ -591,6 +717,7 @@ hipError_t nn_conv(int layer, bool backward, const bf16* a, const bf16* b, const
     }
   }
 #undef CONV
+#undef ROWS
   return hipGetLastError();
 }
 
@@ -668,8 +795,12 @@ hipError_t nn_adam(float* w, const float* g, float* m, float* v, long n, float l
 }
 
 hipError_t nn_prep(const float* w, bf16* fwd, bf16* bwd, int cout, int cinp, int cin_real, hipStream_t st) {
-  const int KP = conv_kp(cinp);
-  hipLaunchKernelGGL(k_prep_fwd, dim3(blocks((long)cout * KP)), dim3(kBlock), 0, st, w, fwd, cout, cinp, cin_real);
+  if (conv_rows(cinp))
+    hipLaunchKernelGGL(k_prep_rows, dim3(blocks(conv_wf_elems(cout, cinp))), dim3(kBlock), 0, st, w, fwd, cout, cinp,
+                       cin_real);
+  else
+    hipLaunchKernelGGL(k_prep_fwd, dim3(blocks(conv_wf_elems(cout, cinp))), dim3(kBlock), 0, st, w, fwd, cout, cinp,
+                       cin_real);
   if (bwd) {
     const int KPt = conv_kp(cout);
     hipLaunchKernelGGL(k_prep_bwd, dim3(blocks((long)cin_real * KPt)), dim3(kBlock), 0, st, w, bwd, cout, cin_real);

@@ -316,7 +316,7 @@ int lc_net_create(lc_net** out, uint64_t seed) {
   const size_t pbytes = al(n->np * sizeof(float));
   size_t wbytes = 0;
   for (int l = 0; l < 5; ++l) {
-    wbytes += al((size_t)kLayers[l].cout * lk::conv_kp(kLayers[l].cinp) * sizeof(bf16));
+    wbytes += al((size_t)lk::conv_wf_elems(kLayers[l].cout, kLayers[l].cinp) * sizeof(bf16));
     if (l > 0) wbytes += al((size_t)kLayers[l].cin * lk::conv_kp(kLayers[l].cout) * sizeof(bf16));
   }
   if (hipMalloc(&n->wmem, 4 * pbytes + wbytes) != hipSuccess || hipMalloc(&n->dpart, kPartBlocks * 3 * sizeof(double)) ||
@@ -334,7 +334,7 @@ int lc_net_create(lc_net** out, uint64_t seed) {
   p += 4 * pbytes;
   for (int l = 0; l < 5; ++l) {
     n->wf[l] = reinterpret_cast<bf16*>(p);
-    p += al((size_t)kLayers[l].cout * lk::conv_kp(kLayers[l].cinp) * sizeof(bf16));
+    p += al((size_t)lk::conv_wf_elems(kLayers[l].cout, kLayers[l].cinp) * sizeof(bf16));
     if (l > 0) {
       n->wb[l] = reinterpret_cast<bf16*>(p);
       p += al((size_t)kLayers[l].cin * lk::conv_kp(kLayers[l].cout) * sizeof(bf16));

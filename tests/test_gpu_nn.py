@@ -210,7 +210,11 @@ def test_guess_matches_oracle(lk, trained):
     print(f"guess eps gpu {eps:.6f} oracle {epso:.6f}; phi0 rel err {e:.2e}")
     assert epso < 0.99
     assert abs(eps - epso) <= 1e-6
-    assert e < 1e-6
+    # same roundings: what differs is where an FP32 sum lands on the other side of a BF16
+    # rounding boundary (one activation off by 2^-8 relative, spread by the layers after it);
+    # 2.5e-5 measured with the wide layers on the row-reuse convolution (< 1e-6 before, other
+    # summation order), bound about 10x that
+    assert e < 3e-4
 
 
 def test_training_reduces_loss(trained):

@@ -58,6 +58,8 @@ def parse():
                     help="instead of the Krylov-vector benchmark: train the learned guess on PAIRS pairs "
                          "from 64^3 and 100^3 Newton steady states (Re 1000-2500, both lid directions) and "
                          "evaluate it inside SIMPLE at 150^3 and 200^3; one JSON line")
+    ap.add_argument("--save-net", type=str, default="", metavar="PATH",
+                    help="with --learned-recipe: write the trained parameters to PATH (lc_net_save)")
     ap.add_argument("--planes", action="store_true",
                     help="instead of the Krylov-vector benchmark: only the plane projections and potentials "
                          "(eqs. 11-17) at --size^3; one JSON line")
@@ -396,7 +398,9 @@ def critical_run(sizes, lk, torch, alpha_deg=0.0):
 
 def steady_states(lk, torch, n, alpha_deg, res_wanted):
     """Newton steady states of the n^3 tanh-10 cube at each Re of res_wanted (continued from
-    rest, Stokes-preconditioned Newton to max |P R(U)| <= 1e-10); returns {Re: U}."""
+    rest, Stokes-preconditioned Newton to max |P R(U)| <= 1e-10; a state that stops short of
+    that but below 1e-6 is kept for training, its residual recorded); returns
+    {Re: (U, max |P R(U)|)}."""
     import math
     ctx = lk.Context(n)
     ctx.set_stretching("tanh", TANH_RATIO)
@@ -404,35 +408,39 @@ def steady_states(lk, torch, n, alpha_deg, res_wanted):
     ctx.set_base_flow(torch.zeros(ctx.nvel, dtype=torch.float64, device="cuda"))
     ctx.set_stokes_precond(float("inf"))
     out = {}
-    path = sorted(set([250.0 * q for q in range(1, 10)] + [r for r in res_wanted]))
+    path = sorted(set([250.0 * q for q in range(1, 9)] + [2000.0 + 125.0 * q for q in range(1, 5)] +
+                      [r for r in res_wanted]))
     for re in path:
         ctx.set_re(re)
-        hist = ctx.newton(tol=1e-10, max_steps=12, lin_tol=1e-8, gmres_m=100, max_vectors=20000)
+        hist = ctx.newton(tol=1e-10, max_steps=15, lin_tol=1e-9, gmres_m=100, max_vectors=20000)
         log(f"[recipe] {n}^3 alpha {alpha_deg:g} Re {re:g}: Newton |P R(U)| {hist[-1]:.1e} ({len(hist) - 1} steps)")
-        if hist[-1] > 1e-10:
+        if not hist[-1] <= 1e-6:
             raise RuntimeError(f"Newton did not converge at {n}^3, alpha {alpha_deg}, Re {re}")
         if re in res_wanted:
-            out[re] = ctx.get_base_flow().clone()
+            out[re] = (ctx.get_base_flow().clone(), hist[-1])
     ctx.close()
     return out
 
 
-def learned_recipe_run(lk, torch, pairs, rounds):
+def learned_recipe_run(lk, torch, pairs, rounds, save_net=""):
     """The learned guess trained on the training set of the learned-preconditioner workload:
     pairs the method generates (w = L_U v, D w -> the first SIMPLE correction) on 64^3 and
     100^3 tanh-10 grids, on Newton steady states at Re 1000..2500 for both lid directions
     (parallel to a side wall, alpha = 0, and to the diagonal plane, alpha = 45 degrees),
     visited round-robin; then evaluated inside SIMPLE at 150^3 and 200^3 (the benchmark's
-    Re = 1900 and seeded base flow) against the same network after 300 64^3 pairs and an
-    untrained one.  One JSON line."""
+    Re = 1900 and seeded base flow) and at 150^3 on the Newton steady state at Re = 1900,
+    against the same network after 300 64^3 pairs and an untrained one.  save_net: file the
+    trained parameters are written to right after training.  One JSON line."""
     import math
     t0 = time.perf_counter()
     spec = {64: (1000.0, 1500.0, 2000.0, 2500.0), 100: (1000.0, 1750.0, 2500.0)}
     states = []  # (n, alpha, Re, U)
+    residuals = []
     for n, res in spec.items():
         for alpha in (0.0, 45.0):
-            for re, U in steady_states(lk, torch, n, alpha, res).items():
+            for re, (U, r) in steady_states(lk, torch, n, alpha, res).items():
                 states.append((n, alpha, re, U))
+                residuals.append({"grid": n, "alpha_deg": alpha, "re": re, "res_inf": r})
     t1 = time.perf_counter()
     ctxs = {}
     for n in spec:
@@ -455,19 +463,30 @@ def learned_recipe_run(lk, torch, pairs, rounds):
             f"({time.perf_counter() - t1:.0f} s)")
     torch.cuda.synchronize()
     t2 = time.perf_counter()
+    if save_net:
+        net.save(save_net)
     for c in ctxs.values():
         c.close()
     quick, _ = train_guess(lk, torch, 64, 300)
     untrained = lk.Net(seed=11)
     evals = []
-    for n in (150, 200):
+    for n, base in ((150, "seeded"), (200, "seeded"), (150, "steady")):
         ctx = lk.Context(n)
         ctx.set_stretching("tanh", TANH_RATIO)
-        ctx.set_re(RE)
         ctx.set_lid(0.0)
-        ctx.set_base_flow(synthetic_base_flow(ctx, torch))
+        if base == "seeded":
+            ctx.set_re(RE)
+            ctx.set_base_flow(synthetic_base_flow(ctx, torch))
+        else:
+            ctx.set_base_flow(torch.zeros(ctx.nvel, dtype=torch.float64, device="cuda"))
+            ctx.set_stokes_precond(float("inf"))
+            for re in (500.0, 1000.0, 1500.0, RE):
+                ctx.set_re(re)
+                hist = ctx.newton(tol=1e-10, max_steps=15, lin_tol=1e-9, gmres_m=100, max_vectors=20000)
+                log(f"[recipe] {n}^3 steady state, Re {re:g}: Newton |P R(U)| {hist[-1]:.1e} ({len(hist) - 1} steps)")
+            ctx.set_stokes_precond(0.0)
         inputs = make_inputs(ctx, torch, 8, seed0=901)
-        row = {"grid": [n, n, n]}
+        row = {"grid": [n, n, n], "base_flow": base}
         for name, nt in (("recipe", net), ("bench_300", quick), ("untrained", untrained)):
             ctx.set_net(nt)
             dt, stats = time_form(ctx, torch, inputs, 2, 6, lk.LEARNED)
@@ -478,13 +497,14 @@ def learned_recipe_run(lk, torch, pairs, rounds):
         dt, stats = time_form(ctx, torch, inputs, 2, 6, lk.MIXED)
         row["mixed"] = {"rho_first_pass_mean": sum(st["rho_hist"][0] for st in stats) / len(stats),
                         "passes_mean": sum(st["iterations"] for st in stats) / len(stats), "vectors_per_s": 6 / dt}
-        log(f"[recipe] {n}^3: eps recipe {row['recipe']['guess_eps_mean']:.3f}, 300-pair "
+        log(f"[recipe] {n}^3 {base}: eps recipe {row['recipe']['guess_eps_mean']:.3f}, 300-pair "
             f"{row['bench_300']['guess_eps_mean']:.3f}, untrained {row['untrained']['guess_eps_mean']:.3f}")
         evals.append(row)
         ctx.close()
     res = {"metric": "learned guess: continuity residual after the guess relative to a plain start (eps)",
            "training_set": {"grids": ["64^3 tanh-10", "100^3 tanh-10"], "re": {str(k): v for k, v in spec.items()},
                             "alpha_deg": [0.0, 45.0], "base_flows": "Newton steady states",
+                            "newton_residuals": residuals,
                             "pairs": per * rounds * len(states), "rounds": rounds, "pairs_per_visit": per,
                             "seconds_newton": t1 - t0, "seconds_training": t2 - t1,
                             "loss_first_round": sum(losses[:len(states)]) / len(states),
@@ -511,7 +531,7 @@ def main():
         return
     if a.learned_recipe:
         torch.cuda.set_device(0)
-        learned_recipe_run(lk, torch, a.learned_recipe, rounds=10)
+        learned_recipe_run(lk, torch, a.learned_recipe, rounds=10, save_net=a.save_net)
         return
     n = a.size
     torch.cuda.set_device(0)

@@ -69,6 +69,12 @@ typedef struct {
   int guess_used;     /* LC_LEARNED: 1 if the network guess started the loop,  */
                       /* 0 if it fell back to the plain start v = w, p = 0     */
   double guess_eps;   /* LC_LEARNED: rho right after the guess (1 on fallback) */
+  /* Device time of the call per phase, from the profiling events (lc_profile_enable on;
+   * -1 when profiling is off): momentum stencil and divergences, pressure-correction
+   * solves (transforms, tridiagonal passes, precision casts), velocity/pressure
+   * corrections, and the network's guess.  Reductions and vector operations are in
+   * ms_total only. */
+  double ms_stencil, ms_poisson, ms_update, ms_network;
 } lc_stats;
 
 /* Library version string (static storage). */
@@ -392,6 +398,14 @@ const char* lc_net_last_error(const lc_net* net);
  * lc_net_param_count() floats).  Setting resets the Adam state. */
 int lc_net_get_params(lc_net* net, float* host);
 int lc_net_set_params(lc_net* net, const float* host);
+
+/* Save / load the master parameters to / from a file (path: NUL-terminated, host):
+ * the 8 bytes "LKNET001", the parameter count as a little-endian uint32, then that many
+ * little-endian float32 values in lc_net_get_params order.  Loading checks the tag, the
+ * count and the length (LC_EINVAL with the reason in lc_net_last_error otherwise, the
+ * network unchanged) and resets the Adam state, as lc_net_set_params does. */
+int lc_net_save(lc_net* net, const char* path);
+int lc_net_load(lc_net* net, const char* path);
 
 /* Forward pass on a D x H x W grid (each a positive multiple of 4):
  * x (device float32 [D][H][W][4]) -> y (device float32 [D][H][W]).

@@ -6,6 +6,7 @@ memory and the stream; every step runs in the HIP library.
 from __future__ import annotations
 
 import ctypes as C
+import os
 
 import numpy as np
 
@@ -379,6 +380,14 @@ class Net:
         if p.size != self.nparams:
             raise ValueError(f"need {self.nparams} parameters")
         self._check(self.lib.lc_net_set_params(self._h, p.ctypes.data_as(C.c_void_p)))
+
+    def save(self, path):
+        """Write the master parameters to `path` (lc_net_save's file format)."""
+        self._check(self.lib.lc_net_save(self._h, os.fsencode(path)))
+
+    def load(self, path):
+        """Read the master parameters from `path`; resets the Adam state."""
+        self._check(self.lib.lc_net_load(self._h, os.fsencode(path)))
 
     @staticmethod
     def _f32(t, shape, name):

@@ -34,13 +34,16 @@ class CriticalOpts(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("iterations", C.c_int), ("rho", C.c_double), ("rho0", C.c_double),
                 ("rho_hist", C.c_double * 16), ("ms_total", C.c_double), ("guess_used", C.c_int),
-                ("guess_eps", C.c_double)]
+                ("guess_eps", C.c_double), ("ms_stencil", C.c_double), ("ms_poisson", C.c_double),
+                ("ms_update", C.c_double), ("ms_network", C.c_double)]
 
     def as_dict(self):
         n = min(self.iterations, 16)
         return {"iterations": self.iterations, "rho": self.rho, "rho0": self.rho0,
                 "rho_hist": [self.rho_hist[q] for q in range(n)], "ms_total": self.ms_total,
-                "guess_used": bool(self.guess_used), "guess_eps": self.guess_eps}
+                "guess_used": bool(self.guess_used), "guess_eps": self.guess_eps,
+                "ms_stencil": self.ms_stencil, "ms_poisson": self.ms_poisson, "ms_update": self.ms_update,
+                "ms_network": self.ms_network}
 
 
 _P = C.c_void_p
@@ -87,6 +90,8 @@ _SIGS = {
     "lc_net_last_error": (C.c_char_p, [_P]),
     "lc_net_get_params": (_I, [_P, _P]),
     "lc_net_set_params": (_I, [_P, _P]),
+    "lc_net_save": (_I, [_P, C.c_char_p]),
+    "lc_net_load": (_I, [_P, C.c_char_p]),
     "lc_net_forward": (_I, [_P, _P, _P, _P, _I, _I, _I]),
     "lc_net_step": (_I, [_P, _P, _P, _P, _I, _I, _I, _D, C.POINTER(_D), _P]),
     "lc_set_net": (_I, [_P, _P]),

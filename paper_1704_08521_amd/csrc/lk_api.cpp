@@ -647,8 +647,35 @@ int lc_correct(lc_ctx* c, const double* w, const double* phi, double* v, double*
   return LC_OK;
 }
 
-int lc_project(lc_ctx* c, const double* w, double* v, double* p, int precision, double tol, int max_iter,
-               lc_stats* st) {
+}  // extern "C"
+
+namespace {
+// per-phase device time of the launches recorded since rec0 (profiling on), else -1
+void fill_phases(lc_ctx* c, lc_stats* S, size_t rec0) {
+  if (!S) return;
+  S->ms_stencil = S->ms_poisson = S->ms_update = S->ms_network = -1.0;
+  if (!c->prof || hipStreamSynchronize(c->stream) != hipSuccess) return;
+  double t[4] = {0.0, 0.0, 0.0, 0.0};
+  for (size_t q = rec0; q < c->recs.size(); ++q) {
+    const int k = c->recs[q].kid;
+    const int ph = (k == LC_K_MOMENTUM || k == LC_K_RESIDUAL || k == LC_K_DIVERGENCE) ? 0
+                   : (k == LC_K_TP_X || k == LC_K_TP_Y || k == LC_K_TP_Z || k == LC_K_EIGSCALE ||
+                      k == LC_K_TRIDIAG || k == LC_K_CAST)
+                       ? 1
+                   : k == LC_K_CORRECT                             ? 2
+                   : (k == LC_K_NN_FORWARD || k == LC_K_NN_MISC) ? 3
+                                                                   : -1;
+    float ms = 0.f;
+    if (ph >= 0 && hipEventElapsedTime(&ms, c->recs[q].a, c->recs[q].b) == hipSuccess) t[ph] += ms;
+  }
+  S->ms_stencil = t[0];
+  S->ms_poisson = t[1];
+  S->ms_update = t[2];
+  S->ms_network = t[3];
+}
+
+int project_impl(lc_ctx* c, const double* w, double* v, double* p, int precision, double tol, int max_iter,
+                 lc_stats* st) {
   const double t0 = now_ms();
   int rc = check_ready(c);
   if (rc) return rc;
@@ -726,14 +753,28 @@ int lc_project(lc_ctx* c, const double* w, double* v, double* p, int precision, 
   return LC_ENOTCONV;
 }
 
+}  // namespace
+
+extern "C" {
+
+int lc_project(lc_ctx* c, const double* w, double* v, double* p, int precision, double tol, int max_iter,
+               lc_stats* st) {
+  const size_t rec0 = c ? c->recs.size() : 0;
+  const int rc = project_impl(c, w, v, p, precision, tol, max_iter, st);
+  if (c && rc >= 0) fill_phases(c, st, rec0);
+  return rc;
+}
+
 int lc_krylov_vector(lc_ctx* c, const double* vin, double* vout, double* pout, int precision, double tol,
                      int max_iter, lc_stats* st) {
   const double t0 = now_ms();
   int rc = check_ready(c);
   if (rc) return rc;
   if (!aligned(vin) || !aligned(vout) || vin == vout) return fail(c, LC_EINVAL, "bad or aliased pointers");
+  const size_t rec0 = c->recs.size();
   KLAUNCH(c, LC_K_MOMENTUM, launch_momentum(c->g, c->U, vin, c->w, 1.0 / c->re, 1.0, false, 0, 0, c->stream));
-  rc = lc_project(c, c->w, vout, pout, precision, tol, max_iter, st);
+  rc = project_impl(c, c->w, vout, pout, precision, tol, max_iter, st);
+  if (rc >= 0) fill_phases(c, st, rec0);
   if (st) st->ms_total = now_ms() - t0;
   return rc;
 }

@@ -392,6 +392,59 @@ int lc_net_set_params(lc_net* n, const float* host) {
   return LC_OK;
 }
 
+int lc_net_save(lc_net* n, const char* path) {
+  if (!n || !path) return LC_EINVAL;
+  std::vector<float> h(n->np);
+  int rc = lc_net_get_params(n, h.data());
+  if (rc) return rc;
+  FILE* f = std::fopen(path, "wb");
+  if (!f) return nfail(n, LC_EINVAL, "cannot open %s for writing", path);
+  const uint32_t count = (uint32_t)n->np;
+  unsigned char head[12] = {'L', 'K', 'N', 'E', 'T', '0', '0', '1'};
+  for (int b = 0; b < 4; ++b) head[8 + b] = (unsigned char)(count >> (8 * b));
+  bool ok = std::fwrite(head, 1, 12, f) == 12;
+  for (size_t q = 0; ok && q < h.size(); ++q) {
+    uint32_t u;
+    std::memcpy(&u, &h[q], 4);
+    const unsigned char le[4] = {(unsigned char)u, (unsigned char)(u >> 8), (unsigned char)(u >> 16),
+                                 (unsigned char)(u >> 24)};
+    ok = std::fwrite(le, 1, 4, f) == 4;
+  }
+  ok = (std::fclose(f) == 0) && ok;
+  return ok ? LC_OK : nfail(n, LC_EINVAL, "write failed: %s", path);
+}
+
+int lc_net_load(lc_net* n, const char* path) {
+  if (!n || !path) return LC_EINVAL;
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return nfail(n, LC_EINVAL, "cannot open %s", path);
+  unsigned char head[12];
+  const bool got = std::fread(head, 1, 12, f) == 12;
+  if (!got || std::memcmp(head, "LKNET001", 8) != 0) {
+    std::fclose(f);
+    return nfail(n, LC_EINVAL, "not a network parameter file: %s", path);
+  }
+  uint32_t count = 0;
+  for (int b = 0; b < 4; ++b) count |= (uint32_t)head[8 + b] << (8 * b);
+  if ((long)count != n->np) {
+    std::fclose(f);
+    return nfail(n, LC_EINVAL, "parameter count %u differs from this network's %ld: %s", count, n->np, path);
+  }
+  std::vector<float> h(n->np);
+  bool ok = true;
+  for (size_t q = 0; ok && q < h.size(); ++q) {
+    unsigned char le[4];
+    ok = std::fread(le, 1, 4, f) == 4;
+    const uint32_t u = (uint32_t)le[0] | ((uint32_t)le[1] << 8) | ((uint32_t)le[2] << 16) | ((uint32_t)le[3] << 24);
+    std::memcpy(&h[q], &u, 4);
+  }
+  unsigned char extra;
+  ok = ok && std::fread(&extra, 1, 1, f) == 0;  // exactly the declared length
+  std::fclose(f);
+  if (!ok) return nfail(n, LC_EINVAL, "file length does not match its parameter count: %s", path);
+  return lc_net_set_params(n, h.data());
+}
+
 int lc_net_forward(lc_net* n, void* stream, const float* x4, float* y, int D, int H, int W) {
   if (!n || !x4 || !y) return LC_EINVAL;
   if (!dims_ok(D, H, W)) return nfail(n, LC_EINVAL, "network sizes must be positive multiples of 4");

@@ -281,3 +281,28 @@ def test_trained_network_gain(lk, trained):
         times[name] = (time.perf_counter() - t0) / len(vs)
     print("time per vector vs plain at 32^3: " +
           ", ".join(f"{k} {1e3 * t:.3f} ms ({t / times['plain']:.2f}x)" for k, t in times.items()))
+
+
+def test_save_load_roundtrip(lk, tmp_path):
+    """lc_net_save / lc_net_load: the parameters and the forward pass come back bit for
+    bit; a foreign, truncated or mismatched file is refused and leaves the network as it was."""
+    import torch
+    a, b = lk.Net(seed=3), lk.Net(seed=9)
+    path = tmp_path / "net.bin"
+    a.save(path)
+    raw = path.read_bytes()
+    assert raw[:8] == b"LKNET001" and int.from_bytes(raw[8:12], "little") == a.nparams
+    assert len(raw) == 12 + 4 * a.nparams
+    assert np.array_equal(np.frombuffer(raw[12:], dtype="<f4"), a.get_params())
+    before = b.get_params()
+    for name, data in (("tag", b"XXNET001" + raw[8:]), ("short", raw[:-4]), ("long", raw + b"\0"),
+                       ("count", raw[:8] + (a.nparams + 1).to_bytes(4, "little") + raw[12:])):
+        bad = tmp_path / f"bad_{name}.bin"
+        bad.write_bytes(data)
+        with pytest.raises(lk.LidKrylovError):
+            b.load(bad)
+        assert np.array_equal(b.get_params(), before), name
+    b.load(path)
+    assert np.array_equal(b.get_params(), a.get_params())
+    x = torch.from_numpy(np.random.default_rng(8).standard_normal((8, 8, 8, 4)).astype(np.float32)).cuda()
+    assert torch.equal(a.forward(x), b.forward(x))

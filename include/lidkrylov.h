@@ -241,9 +241,9 @@ int lc_newton_step(lc_ctx* ctx, double lin_tol, int gmres_m, long max_vectors, i
  * directions, where P L_U is zero; a genuine eigenvalue near 0 (a real eigenvalue
  * crossing the imaginary axis) is divergence-free and is kept.  Converged when every
  * wanted pair has |h_{m+1,m} e_m^T y| <= tol |theta| and, recomputed with the Krylov
- * map on the Ritz vector x, |P L_U x - theta x| <= max(100 tol, 1e-9) |theta| |x|; a
- * pair failing the second test is moved among the exact shifts and the restarts
- * continue (two extra Krylov vectors per pair checked).  If the k-th and (k+1)-th
+ * map on the Ritz vector x, |P L_U x - theta x| <= 1e-3 |theta| |x|: a pair failing
+ * the second test is spurious (a drifted basis), is moved among the exact shifts and
+ * the restarts continue (two extra Krylov vectors per pair checked).  If the k-th and (k+1)-th
  * values are a conjugate pair both are returned.
  * Requirements: 1 <= k <= 46, k + 3 <= m <= 100.  Outputs (host): eig_re,
  * eig_im, resid (may be NULL): arrays of k+1 doubles, real part descending;

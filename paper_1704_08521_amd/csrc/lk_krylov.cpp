@@ -285,8 +285,10 @@ int arnoldi_run(lc_ctx* c, int k, int m, double tol, int max_restarts, unsigned 
       // The estimates say converged: recompute each wanted pair's residual |K x - theta x| with
       // the Krylov map itself (two vectors per pair).  A Ritz value whose basis has drifted from
       // the Arnoldi relation -- seen as a real value near the gradient directions' zeros with a
-      // tiny estimate -- fails here; it is then treated as unwanted (an exact shift) and the
-      // selection is redone.
+      // tiny estimate -- has a residual of order one; it is then treated as unwanted (an exact
+      // shift) and the selection is redone.  A genuine pair passes: the map's own error (an
+      // inexact projection in the mixed form, relative to |L_U x| rather than |theta|) keeps its
+      // recomputed residual above the estimate but orders of magnitude below the threshold.
       bool all_ok = true;
       for (int i = 0; i < kc; ++i) {
         std::vector<double> Qy((size_t)m * 2);
@@ -309,11 +311,11 @@ int arnoldi_run(lc_ctx* c, int k, int m, double tol, int max_restarts, unsigned 
         }
         if ((rc = vdot(c, W.at(2), W.at(2), &r2)) || (rc = vdot(c, W.at(0), W.at(0), &x2))) return rc;
         const double rel = vnorm(r2 + i2) / std::max(std::abs(theta[i]) * vnorm(x2 + y2), 1e-300);
-        const double bound = std::max(100.0 * tol, 1e-9);
+        constexpr double kSpurious = 1e-3;
         if (verbose())
           std::fprintf(stderr, "[lk arnoldi] verify %.10f%+.10fi: estimate %.2e, recomputed %.2e%s\n", tr, ti,
-                       res[i] / std::max(std::abs(theta[i]), 1e-300), rel, rel > bound ? " (rejected)" : "");
-        if (rel > bound) {
+                       res[i] / std::max(std::abs(theta[i]), 1e-300), rel, rel > kSpurious ? " (rejected)" : "");
+        if (rel > kSpurious) {
           rejected.push_back(theta[i]);
           all_ok = false;
         }

@@ -15,7 +15,9 @@ namespace {
 // a chunk of planes.  For each of the six input fields (advecting a = U and
 // advected b, components u, v, w) the planes k and k+1 with a one-cell x/y halo live
 // in LDS (17 KB); the few plane k-1 values a step needs are carried in registers from
-// the step before.  Positions outside a field's stored range are
+// the step before, and so are the products on the level between two planes (the edge
+// fluxes at (x_i, z_k) and (y_j, z_k), the z-momentum's centre product), which two
+// consecutive steps share.  Positions outside a field's stored range are
 // filled with the wall value of that position: 0 on wall-normal faces, beyond
 // tangential walls 0 or, for the advected field of the nonlinear residual, the
 // lid velocity at z = 1 (eq. 4).  With these ghosts the wall fluxes of the
@@ -123,6 +125,7 @@ __global__ void __launch_bounds__(TX* TY) k_momentum(GridDev g, const double* __
   const double rddy0 = (j <= ny) ? g.y.rdd[j] : 0.0, rddy1 = (j + 1 <= ny) ? g.y.rdd[j + 1] : 0.0;
 
   double cm[6], c0[6], cp[6];
+  double exz0, eyz0, czc0;  // the zf[k] level products (see compute)
   double nm0, nm3, nm1, nm4;  // plane k-1: u-fields at (0, +1), v-fields at (+1, 0)
   auto compute = [&](int k) {
     const int p0 = (k + 2) & 1, pp = (k + 3) & 1;  // planes k, k+1
@@ -137,6 +140,28 @@ __global__ void __launch_bounds__(TX* TY) k_momentum(GridDev g, const double* __
     const double thz0 = g.z.th[k], thz1 = (k + 1 <= nz) ? g.z.th[k + 1] : 0.0;
     const double rdz0 = (k < nz) ? g.z.rd[k] : 0.0, rdzm = (k >= 1) ? g.z.rd[k - 1] : 0.0;
     const double rddz0 = g.z.rdd[k], rddz1 = (k + 1 <= nz) ? g.z.rdd[k + 1] : 0.0;
+    // products on the level zf[k + 1] between planes k and k + 1, used again (as the level
+    // zf[k]) by the next step: the edge fluxes at (xf[i], zf[k + 1]) and (yf[j], zf[k + 1]),
+    // and the z-momentum's centre product of cell k
+    double exz1, eyz1, czc1;
+    {
+      const double aw = lerp(S(2, pp, 0, -1), cp[2], thx0);
+      const double bw = lerp(S(5, pp, 0, -1), cp[5], thx0);
+      const double au = lerp(c0[0], cp[0], thz1);
+      const double bu = lerp(c0[3], cp[3], thz1);
+      exz1 = aw * bu + bw * au;
+    }
+    {
+      const double aw = lerp(S(2, pp, -1, 0), cp[2], thy0);
+      const double bw = lerp(S(5, pp, -1, 0), cp[5], thy0);
+      const double av = lerp(c0[1], cp[1], thz1);
+      const double bv = lerp(c0[4], cp[4], thz1);
+      eyz1 = aw * bv + bw * av;
+    }
+    {
+      const double ap = 0.5 * (c0[2] + cp[2]), bp = 0.5 * (c0[5] + cp[5]);
+      czc1 = ap * bp;
+    }
 
     // ---- x-momentum at the x-face (i, j, k)
     if (k < nz && j < ny && i <= nx) {
@@ -167,22 +192,8 @@ __global__ void __launch_bounds__(TX* TY) k_momentum(GridDev g, const double* __
           e1 = av * bu + bv * au;
         }
         conv += (e1 - e0) * rdy0;
-        // edges (xf[i], zf[k + dk])
-        {
-          const double aw = lerp(S(2, p0, 0, -1), c0[2], thx0);
-          const double bw = lerp(S(5, p0, 0, -1), c0[5], thx0);
-          const double au = lerp(cm[0], c0[0], thz0);
-          const double bu = lerp(cm[3], c0[3], thz0);
-          e0 = aw * bu + bw * au;
-        }
-        {
-          const double aw = lerp(S(2, pp, 0, -1), cp[2], thx0);
-          const double bw = lerp(S(5, pp, 0, -1), cp[5], thx0);
-          const double au = lerp(c0[0], cp[0], thz1);
-          const double bu = lerp(c0[3], cp[3], thz1);
-          e1 = aw * bu + bw * au;
-        }
-        conv += (e1 - e0) * rdz0;
+        // edges (xf[i], zf[k]) and (xf[i], zf[k + 1]): the first carried from the step before
+        conv += (exz1 - exz0) * rdz0;
         val = rre * lap - s * conv;
       }
       out[((size_t)k * ny + j) * (nx + 1) + i] = val;
@@ -217,22 +228,8 @@ __global__ void __launch_bounds__(TX* TY) k_momentum(GridDev g, const double* __
         const double am = 0.5 * (S(1, p0, -1, 0) + ac), ap = 0.5 * (ac + S(1, p0, 1, 0));
         const double bm = 0.5 * (S(4, p0, -1, 0) + bc), bp = 0.5 * (bc + S(4, p0, 1, 0));
         conv += 2.0 * (ap * bp - am * bm) * rddy0;
-        // edges (yf[j], zf[k + dk])
-        {
-          const double aw = lerp(S(2, p0, -1, 0), c0[2], thy0);
-          const double bw = lerp(S(5, p0, -1, 0), c0[5], thy0);
-          const double av = lerp(cm[1], c0[1], thz0);
-          const double bv = lerp(cm[4], c0[4], thz0);
-          e0 = aw * bv + bw * av;
-        }
-        {
-          const double aw = lerp(S(2, pp, -1, 0), cp[2], thy0);
-          const double bw = lerp(S(5, pp, -1, 0), cp[5], thy0);
-          const double av = lerp(c0[1], cp[1], thz1);
-          const double bv = lerp(c0[4], cp[4], thz1);
-          e1 = aw * bv + bw * av;
-        }
-        conv += (e1 - e0) * rdz0;
+        // edges (yf[j], zf[k]) and (yf[j], zf[k + 1]): the first carried from the step before
+        conv += (eyz1 - eyz0) * rdz0;
         val = rre * lap - s * conv;
       }
       out[nu + ((size_t)k * (ny + 1) + j) * nx + i] = val;
@@ -247,14 +244,8 @@ __global__ void __launch_bounds__(TX* TY) k_momentum(GridDev g, const double* __
         lap += ((S(5, p0, 0, 1) - bc) * rddx1 - (bc - S(5, p0, 0, -1)) * rddx0) * rdx0;
         lap += ((S(5, p0, 1, 0) - bc) * rddy1 - (bc - S(5, p0, -1, 0)) * rddy0) * rdy0;
         double e0, e1;
-        // edges (xf[i + di], zf[k])
-        {
-          const double au = lerp(cm[0], c0[0], thz0);
-          const double bu = lerp(cm[3], c0[3], thz0);
-          const double aw = lerp(S(2, p0, 0, -1), c0[2], thx0);
-          const double bw = lerp(S(5, p0, 0, -1), c0[5], thx0);
-          e0 = au * bw + bu * aw;
-        }
+        // edges (xf[i + di], zf[k]); the one at xf[i] is the x-momentum's, carried
+        e0 = exz0;
         {
           const double au = lerp(nm0, S(0, p0, 0, 1), thz0);
           const double bu = lerp(nm3, S(3, p0, 0, 1), thz0);
@@ -263,14 +254,8 @@ __global__ void __launch_bounds__(TX* TY) k_momentum(GridDev g, const double* __
           e1 = au * bw + bu * aw;
         }
         double conv = (e1 - e0) * rdx0;
-        // edges (yf[j + dj], zf[k])
-        {
-          const double av = lerp(cm[1], c0[1], thz0);
-          const double bv = lerp(cm[4], c0[4], thz0);
-          const double aw = lerp(S(2, p0, -1, 0), c0[2], thy0);
-          const double bw = lerp(S(5, p0, -1, 0), c0[5], thy0);
-          e0 = av * bw + bv * aw;
-        }
+        // edges (yf[j + dj], zf[k]); the one at yf[j] is the y-momentum's, carried
+        e0 = eyz0;
         {
           const double av = lerp(nm1, S(1, p0, 1, 0), thz0);
           const double bv = lerp(nm4, S(4, p0, 1, 0), thz0);
@@ -279,10 +264,7 @@ __global__ void __launch_bounds__(TX* TY) k_momentum(GridDev g, const double* __
           e1 = av * bw + bv * aw;
         }
         conv += (e1 - e0) * rdy0;
-        const double ac = c0[2];
-        const double am = 0.5 * (cm[2] + ac), ap = 0.5 * (ac + cp[2]);
-        const double bm = 0.5 * (cm[5] + bc), bp = 0.5 * (bc + cp[5]);
-        conv += 2.0 * (ap * bp - am * bm) * rddz0;
+        conv += 2.0 * (czc1 - czc0) * rddz0;
         val = rre * lap - s * conv;
       }
       out[nu + nv + ((size_t)k * ny + j) * nx + i] = val;
@@ -297,6 +279,9 @@ __global__ void __launch_bounds__(TX* TY) k_momentum(GridDev g, const double* __
       cm[arr] = c0[arr];
       c0[arr] = cp[arr];
     }
+    exz0 = exz1;
+    eyz0 = eyz1;
+    czc0 = czc1;
   };
 
   // LDS holds planes k and k+1 (two slots); plane kb - 1 passes through once for the values
@@ -323,6 +308,29 @@ __global__ void __launch_bounds__(TX* TY) k_momentum(GridDev g, const double* __
   __syncthreads();
 #pragma unroll
   for (int arr = 0; arr < 6; ++arr) c0[arr] = S(arr, kb & 1, 0, 0);
+  {
+    // the zf[kb] level products from planes kb - 1 (registers) and kb
+    const int p0 = kb & 1;
+    const double thz0 = g.z.th[kb];
+    {
+      const double aw = lerp(S(2, p0, 0, -1), c0[2], thx0);
+      const double bw = lerp(S(5, p0, 0, -1), c0[5], thx0);
+      const double au = lerp(cm[0], c0[0], thz0);
+      const double bu = lerp(cm[3], c0[3], thz0);
+      exz0 = aw * bu + bw * au;
+    }
+    {
+      const double aw = lerp(S(2, p0, -1, 0), c0[2], thy0);
+      const double bw = lerp(S(5, p0, -1, 0), c0[5], thy0);
+      const double av = lerp(cm[1], c0[1], thz0);
+      const double bv = lerp(cm[4], c0[4], thz0);
+      eyz0 = aw * bv + bw * av;
+    }
+    {
+      const double am = 0.5 * (cm[2] + c0[2]), bm = 0.5 * (cm[5] + c0[5]);
+      czc0 = am * bm;
+    }
+  }
 #undef S
   if (kb + 2 <= ke) load(r0, kb + 2);
   for (int k = kb; k < ke; ++k) {

@@ -8,7 +8,8 @@ GPU eigenpair (lam, x) with its own Krylov-vector map A = P L_U: the relative re
 plain FP64 projections, mixed (FP32 solves in FP64 refinement) and learned (network guess,
 then mixed passes) -- must give the same leading eigenvalues to 1e-6 relative.
 
-LK_LONG=1 adds the same certification at 200^3 (the benchmark grid; several minutes).
+LK_LONG=1 adds the same certification at 100^3 (a few minutes) and at 200^3 (the benchmark
+grid: Newton continuation and three Arnoldi runs there take longer than one GPU call allows).
 """
 import os
 
@@ -64,8 +65,13 @@ def run_forms(n, re, kind, k, m, restarts):
     net.train(c, steps=40, lr=2e-3, seed=3)
     c.set_net(net)
     lead = {}
-    for name, prec, ptol in (("plain", lk.FP64, 1e-12), ("mixed", lk.MIXED, 1e-10), ("learned", lk.LEARNED, 1e-10)):
-        out = c.arnoldi_leading(k=k, m=m, tol=1e-8, max_restarts=restarts, seed=5, precision=prec, proj_tol=ptol,
+    # Ritz tolerance per form: the mixed and learned maps project to rho <= 1e-10 only, and
+    # that inexactness (relative to |L_U x|, orders above |lambda x|) leaves a floor near 3e-8
+    # on the Ritz estimate (measured: 2.7e-8 after 600 restarts at 64^3); 1e-7 still fixes
+    # lambda far inside the 1e-6 target, which the certificate below checks independently
+    for name, prec, ptol, tol in (("plain", lk.FP64, 1e-12, 1e-8), ("mixed", lk.MIXED, 1e-10, 1e-7),
+                                  ("learned", lk.LEARNED, 1e-10, 1e-7)):
+        out = c.arnoldi_leading(k=k, m=m, tol=tol, max_restarts=restarts, seed=5, precision=prec, proj_tol=ptol,
                                 vectors=True)
         lam = out["eig"][0]
         x = host(out["vectors"][0][0]) + 1j * host(out["vectors"][1][0])
@@ -88,6 +94,11 @@ def run_forms(n, re, kind, k, m, restarts):
 def test_leading_eigenvalues_every_form_64():
     # k = 1: the leading eigenvalue (with its conjugate when complex)
     run_forms(64, 1000.0, "tanh", k=1, m=100, restarts=600)
+
+
+@pytest.mark.skipif(os.environ.get("LK_LONG") != "1", reason="a few minutes: run with LK_LONG=1")
+def test_leading_eigenvalues_every_form_100():
+    run_forms(100, 1000.0, "tanh", k=1, m=100, restarts=800)
 
 
 @pytest.mark.skipif(os.environ.get("LK_LONG") != "1", reason="several minutes: run with LK_LONG=1")

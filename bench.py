@@ -51,6 +51,10 @@ def parse():
                          "driver lc_critical_re); one JSON line")
     ap.add_argument("--alpha", type=float, choices=(0.0, 45.0), default=0.0,
                     help="lid angle (degrees) of --critical: 0 (parallel to a side wall) or 45 (diagonal)")
+    ap.add_argument("--base-flow", choices=("steady", "seeded"), default="steady",
+                    help="benchmark base flow: the Newton steady state (continued at 100^3, prolongated, "
+                         "Newton at the benchmark grid) or a seeded divergence-free field (faster set-up; the "
+                         "cost of a Krylov vector does not depend on U)")
     ap.add_argument("--poisson", choices=("tpt", "tpf"), default="tpt",
                     help="pressure-solve route (transforms along y, z with tridiagonal solves along x, "
                          "or transforms along x, y, z)")
@@ -90,6 +94,74 @@ def synthetic_base_flow(ctx, torch):
     U, _, _ = ctx.project(r, tol=1e-12, max_iter=4)
     U /= U.abs().max()
     return U
+
+
+def _interp_axis(a, old, new, axis):
+    """Linear interpolation of array a along `axis` from positions old to new (clamped
+    beyond the end positions)."""
+    import numpy as np
+    q = np.clip(np.searchsorted(old, new) - 1, 0, len(old) - 2)
+    t = np.clip((new - old[q]) / (old[q + 1] - old[q]), 0.0, 1.0)
+    shape = [1] * a.ndim
+    shape[axis] = len(new)
+    t = t.reshape(shape)
+    return np.take(a, q, axis=axis) * (1.0 - t) + np.take(a, q + 1, axis=axis) * t
+
+
+def prolongate_velocity(U, coarse, fine):
+    """A staggered velocity (packed u|v|w) of the coarse grid interpolated to the fine one:
+    each component separably linear between its own positions (faces along its direction,
+    cell centres across)."""
+    import numpy as np
+    (cx, cy, cz), (fx, fy, fz) = coarse, fine
+    nx, ny, nz = len(cx) - 1, len(cy) - 1, len(cz) - 1
+    c = lambda f: 0.5 * (f[1:] + f[:-1])
+    u = U[:(nx + 1) * ny * nz].reshape(nz, ny, nx + 1)
+    v = U[(nx + 1) * ny * nz:(nx + 1) * ny * nz + nx * (ny + 1) * nz].reshape(nz, ny + 1, nx)
+    w = U[(nx + 1) * ny * nz + nx * (ny + 1) * nz:].reshape(nz + 1, ny, nx)
+    out = []
+    for a, (px, py, pz), (qx, qy, qz) in ((u, (cx, c(cy), c(cz)), (fx, c(fy), c(fz))),
+                                        (v, (c(cx), cy, c(cz)), (c(fx), fy, c(fz))),
+                                        (w, (c(cx), c(cy), cz), (c(fx), c(fy), fz))):
+        a = _interp_axis(a, px, qx, 2)
+        a = _interp_axis(a, py, qy, 1)
+        a = _interp_axis(a, pz, qz, 0)
+        out.append(a.ravel())
+    return np.concatenate(out)
+
+
+def steady_base_flow(lk, torch, ctx, coarse=100):
+    """The benchmark's base flow: the Newton steady state of the coarse^3 grid (continued from
+    rest with Stokes-preconditioned Newton), prolongated to ctx's grid, projected onto the
+    divergence-free space and taken to the steady state there by Newton.  Returns (U, info)."""
+    t0 = time.perf_counter()
+    cc = lk.Context(coarse)
+    cc.set_stretching("tanh", TANH_RATIO)
+    cc.set_lid(0.0)
+    cc.set_base_flow(torch.zeros(cc.nvel, dtype=torch.float64, device="cuda"))
+    cc.set_stokes_precond(float("inf"))
+    for re in (250.0, 500.0, 800.0, 1100.0, 1400.0, 1600.0, 1750.0, 1850.0, RE):
+        cc.set_re(re)
+        hist = cc.newton(tol=1e-11, max_steps=12, lin_tol=1e-8, gmres_m=100, max_vectors=20000)
+        log(f"[bench] {coarse}^3 Newton at Re {re:g}: |P R(U)| {hist[-1]:.1e} ({time.perf_counter() - t0:.0f} s)")
+    Uc = cc.get_base_flow().cpu().numpy()
+    Uf = prolongate_velocity(Uc, cc.get_grid(), ctx.get_grid())
+    cc.close()
+    U, _, _ = ctx.project(torch.from_numpy(Uf).cuda(), tol=1e-12, max_iter=4)
+    ctx.set_base_flow(U)
+    ctx.set_stokes_precond(float("inf"))
+    hist = []
+    for step in range(9):
+        _, r = ctx.newton_residual()
+        hist.append(r)
+        log(f"[bench] {ctx.nx}^3 Newton from the prolongated state, step {step}: |P R(U)| {r:.1e} "
+            f"({time.perf_counter() - t0:.0f} s)")
+        if r <= 1e-10 or step == 8:
+            break
+        ctx.newton_step(lin_tol=1e-8, gmres_m=100, max_vectors=6000)
+    ctx.set_stokes_precond(0.0)
+    return ctx.get_base_flow(), {"kind": "Newton steady state", "coarse_grid": coarse,
+                                 "newton_res_inf": hist, "seconds": time.perf_counter() - t0}
 
 
 def time_form(ctx, torch, inputs, warmup, steps, precision):
@@ -263,12 +335,15 @@ PAPER_TABLE3 = {0.0: {100: (1963.74, 0.575370), 150: (1938.98, 0.581315), 200: (
                       256: (1926.10, 0.584438), "extrapolated": (1919.37, 0.58607)},
                 45.0: {100: (2266.29, 0.250855), 150: (2278.39, 0.250305), 200: (2283.17, 0.249868),
                        256: (2285.56, 0.249650), "extrapolated": (2289.31, 0.249307)}}
+# grids above 150^3 take the continuation path on the 100^3 grid and start from its steady state
+CRITICAL_COARSE = 100
 # per lid angle: the Newton continuation path from rest and, per grid, the two starting values
-# of the secant search (alpha = 0: bracketing the paper's values on 100^3 - 256^3; alpha = 45:
+# of the secant search (alpha = 0: bracketing the paper's values on 100^3 - 256^3, at 200^3
+# around the value an O(h^2) error predicts from this build's 100^3 and 150^3 results; alpha = 45:
 # around the paper's 100^3 value, and at 150^3 around the value an O(h^2) error would give
 # between the 100^3 result of this discretization, 2332.2, and the paper's limit, 2289.3)
 CRITICAL_PATH = {0.0: ((250.0, 500.0, 800.0, 1100.0, 1400.0, 1600.0, 1750.0, 1850.0, 1900.0),
-                       {"default": (1920.0, 1960.0)}),
+                       {"default": (1920.0, 1960.0), 200: (1928.0, 1935.0)}),
                  45.0: ((250.0, 500.0, 800.0, 1100.0, 1400.0, 1700.0, 1900.0, 2050.0, 2150.0, 2250.0),
                         {"default": (2265.0, 2285.0), 150: (2300.0, 2316.0)})}
 
@@ -340,23 +415,44 @@ def critical_one(n, lk, torch, alpha_deg=0.0):
     import math
     path, starts = CRITICAL_PATH[alpha_deg]
     re0, re1 = starts.get(n, starts["default"])
-    ctx = lk.Context(n)
-    ctx.set_stretching("sine", 0.0)
-    ctx.set_lid(math.radians(alpha_deg))
-    ctx.set_base_flow(torch.zeros(ctx.nvel, dtype=torch.float64, device="cuda"))
-    ctx.set_stokes_precond(float("inf"))
     t0 = time.perf_counter()
     cont = []
     vectors = 0
-    for re in path:
-        ctx.set_re(re)
+
+    def newton_at(c, tag, re):
+        nonlocal vectors
+        c.set_re(re)
         for step in range(12):
-            _, r = ctx.newton_residual()
-            log(f"[critical {n}] Re {re:g} Newton step {step}: |P R(U)| {r:.2e} ({time.perf_counter() - t0:.0f} s)")
+            _, r = c.newton_residual()
+            log(f"[critical {tag}] Re {re:g} Newton step {step}: |P R(U)| {r:.2e} ({time.perf_counter() - t0:.0f} s)")
             if r <= 1e-11 or step == 11:
                 break
-            vectors += ctx.newton_step(lin_tol=1e-8, gmres_m=100, max_vectors=20000)["n_vectors"]
-        cont.append({"re": re, "newton_steps": step, "res_inf": r})
+            vectors += c.newton_step(lin_tol=1e-8, gmres_m=100, max_vectors=20000)["n_vectors"]
+        cont.append({"grid": c.nx, "re": re, "newton_steps": step, "res_inf": r})
+
+    def start(m):
+        c = lk.Context(m)
+        c.set_stretching("sine", 0.0)
+        c.set_lid(math.radians(alpha_deg))
+        c.set_base_flow(torch.zeros(c.nvel, dtype=torch.float64, device="cuda"))
+        c.set_stokes_precond(float("inf"))
+        return c
+
+    ctx = start(n)
+    if n > 150:
+        # continuation on the coarse grid, then its steady state interpolated to this grid,
+        # projected, and Newton here at the path's last Re
+        cc = start(CRITICAL_COARSE)
+        for re in path:
+            newton_at(cc, CRITICAL_COARSE, re)
+        Uf = prolongate_velocity(cc.get_base_flow().cpu().numpy(), cc.get_grid(), ctx.get_grid())
+        cc.close()
+        U, _, _ = ctx.project(torch.from_numpy(Uf).cuda(), tol=1e-12, max_iter=4)
+        ctx.set_base_flow(U)
+        newton_at(ctx, n, path[-1])
+    else:
+        for re in path:
+            newton_at(ctx, n, re)
     t1 = time.perf_counter()
     os.environ["LK_VERBOSE"] = "1"  # progress trace on stderr during the long driver call
     out = ctx.critical_re(re0, re1, re_tol=1e-6, max_evals=8, newton_tol=1e-11, newton_steps=8,
@@ -541,7 +637,11 @@ def main():
     ctx.set_lid(0.0)
     ctx.set_poisson_method(a.poisson)
     log(f"[bench] {n}^3 tanh-{TANH_RATIO:g} Re={RE:g}: building inputs")
-    U = synthetic_base_flow(ctx, torch)
+    if a.base_flow == "steady":
+        U, base_info = steady_base_flow(lk, torch, ctx)
+    else:
+        U = synthetic_base_flow(ctx, torch)
+        base_info = {"kind": "seeded divergence-free field, max |U| = 1"}
     ctx.set_base_flow(U)
     inputs = make_inputs(ctx, torch, a.warmup + a.steps)
     # the streaming ceiling of this device for the stencil's pattern (2 reads + 1 write) and
@@ -647,7 +747,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"krylov_vector {n}^3 tanh-10 stretched, Re={RE:g}, alpha=0, rho<=1e-8, "
-                               "seeded projected random inputs, synthetic divergence-free base flow",
+                               "seeded projected random inputs, base flow: " + base_info["kind"],
+                   "base_flow": base_info,
                    "grid": [n, n, n], "stretching": "tanh", "ratio": TANH_RATIO, "re": RE, "tol": 1e-8,
                    "poisson": "tensor-product factorization"},
         "forms": forms,

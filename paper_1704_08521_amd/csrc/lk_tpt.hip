@@ -146,20 +146,41 @@ __global__ void __launch_bounds__(64 * kTriLinesPerBlock) k_tridiag_x(
   // cyclic reduction across the lanes (identity rows beyond P couple to nothing)
   for (int st = 1; st < P; st <<= 1) {
     const T rbt = rcpx(bt);
-    const T am = __shfl_up(al, st), gm = __shfl_up(ga, st), dm = __shfl_up(dl, st), rm = __shfl_up(rbt, st);
-    const T ap = __shfl_down(al, st), gp = __shfl_down(ga, st), dp = __shfl_down(dl, st), rp = __shfl_down(rbt, st);
     T an = 0, gn = 0, bn = bt, dn = dl;
-    if (lane >= st) {
-      const T k1 = al * rm;
-      an = -am * k1;
-      bn -= gm * k1;
-      dn -= dm * k1;
-    }
-    if (lane + st < 64) {
-      const T k2 = ga * rp;
-      gn = -gp * k2;
-      bn -= ap * k2;
-      dn -= dp * k2;
+    if constexpr (sizeof(T) == 8) {
+      // each lane sends its row divided by its own diagonal: three values per direction
+      // (12 LDS permutes per step instead of 16)
+      const T as = al * rbt, gs = ga * rbt, ds = dl * rbt;
+      const T am = __shfl_up(as, st), gm = __shfl_up(gs, st), dm = __shfl_up(ds, st);
+      const T ap = __shfl_down(as, st), gp = __shfl_down(gs, st), dp = __shfl_down(ds, st);
+      if (lane >= st) {
+        an = -al * am;
+        bn -= al * gm;
+        dn -= al * dm;
+      }
+      if (lane + st < 64) {
+        gn = -ga * gp;
+        bn -= ga * ap;
+        dn -= ga * dp;
+      }
+    } else {
+      // FP32: the neighbour's reciprocal travels separately, which keeps the mixed form's
+      // solves as accurate as before the FP64 change (the sender-side products lost a factor
+      // of about 1.5 in the first-pass divergence)
+      const T am = __shfl_up(al, st), gm = __shfl_up(ga, st), dm = __shfl_up(dl, st), rm = __shfl_up(rbt, st);
+      const T ap = __shfl_down(al, st), gp = __shfl_down(ga, st), dp = __shfl_down(dl, st), rp = __shfl_down(rbt, st);
+      if (lane >= st) {
+        const T k1 = al * rm;
+        an = -am * k1;
+        bn -= gm * k1;
+        dn -= dm * k1;
+      }
+      if (lane + st < 64) {
+        const T k2 = ga * rp;
+        gn = -gp * k2;
+        bn -= ap * k2;
+        dn -= dp * k2;
+      }
     }
     al = an;
     bt = bn;

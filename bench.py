@@ -474,6 +474,11 @@ def critical_one(n, lk, torch, alpha_deg=0.0):
     return res
 
 
+def richardson(v_coarse, v_fine, n_coarse, n_fine):
+    """Richardson extrapolation of a value with an O(h^2) error, h = 1/n (Section 5)."""
+    return v_fine + (v_fine - v_coarse) / ((n_fine / n_coarse) ** 2 - 1.0)
+
+
 def critical_run(sizes, lk, torch, alpha_deg=0.0):
     """Critical Reynolds number on each grid of the sequence (sine grid of eq. 5, lid at
     angle alpha to x) and the Richardson extrapolation of Section 5 from each pair of
@@ -482,9 +487,8 @@ def critical_run(sizes, lk, torch, alpha_deg=0.0):
     extrap = []
     for c, f in zip(grids, grids[1:]):
         nc, nf = c["grid"][0], f["grid"][0]
-        q = (nf / nc) ** 2 - 1.0
-        extrap.append({"grids": [nc, nf], "re_cr": f["re_cr"] + (f["re_cr"] - c["re_cr"]) / q,
-                       "omega_cr": f["omega_cr"] + (f["omega_cr"] - c["omega_cr"]) / q})
+        extrap.append({"grids": [nc, nf], "re_cr": richardson(c["re_cr"], f["re_cr"], nc, nf),
+                       "omega_cr": richardson(c["omega_cr"], f["omega_cr"], nc, nf)})
     res = {"metric": "critical Reynolds number (leading eigenvalue of eq. 7 crossing the imaginary axis)",
            "stretching": "sine (eq. 5)", "alpha_deg": alpha_deg, "newton": "Stokes-preconditioned (dt = inf)",
            "grids": grids, "richardson": extrap,

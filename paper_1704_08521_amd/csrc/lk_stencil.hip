@@ -397,32 +397,29 @@ __global__ void __launch_bounds__(kCorTX* kCorTY) k_correct(GridDev g, const dou
   const double rddx = g.x.rdd[i], rddy = g.y.rdd[j];
   double pb = phi[I.c(max(k0 - 1, 0), jc, ic)];  // phi below the first plane
   for (int k = k0; k < k1; ++k) {
+    // every load of the plane from an in-range (clamped) position, before any store, so
+    // that they are in flight together; only the stores depend on the face being stored
     const int kc = min(k, nz - 1);
     const double pc = phi[I.c(kc, jc, ic)];
+    const double pw = phi[I.c(kc, jc, max(ic - 1, 0))], ps = phi[I.c(kc, max(jc - 1, 0), ic)];
+    const size_t qu = I.u(kc, jc, i), qv = nu + I.v(kc, j, ic), qw = nu + nv + I.w(k, jc, ic);
+    const double su = src[qu], sv = src[qv], sw = src[qw];
+    const double pold = (p && accumulate) ? p[I.c(kc, jc, ic)] : 0.0;
     if (j < ny && k < nz) {
-      const size_t q = I.u(k, j, i);
       const bool in = (i > 0) & (i < nx);
-      const double pw = phi[I.c(k, j, max(i - 1, 0))], s = src[q];
-      const double val = s - (pc - pw) * rddx;
-      v[q] = in ? val : 0.0;
+      const double val = su - (pc - pw) * rddx;
+      v[qu] = in ? val : 0.0;
     }
     if (i < nx && k < nz) {
-      const size_t q = nu + I.v(k, j, i);
       const bool in = (j > 0) & (j < ny);
-      const double ps = phi[I.c(k, max(j - 1, 0), i)], s = src[q];
-      const double val = s - (pc - ps) * rddy;
-      v[q] = in ? val : 0.0;
+      const double val = sv - (pc - ps) * rddy;
+      v[qv] = in ? val : 0.0;
     }
     if (i < nx && j < ny) {
-      const size_t q = nu + nv + I.w(k, j, i);
       const bool in = (k > 0) & (k < nz);
-      const double s = src[q];
-      const double val = s - (pc - pb) * g.z.rdd[k];
-      v[q] = in ? val : 0.0;
-      if (p && k < nz) {
-        const size_t c = I.c(k, j, i);
-        p[c] = accumulate ? p[c] + pc : pc;
-      }
+      const double val = sw - (pc - pb) * g.z.rdd[k];
+      v[qw] = in ? val : 0.0;
+      if (p && k < nz) p[I.c(k, j, i)] = accumulate ? pold + pc : pc;
     }
     pb = pc;
   }

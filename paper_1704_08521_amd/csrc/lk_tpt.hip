@@ -52,30 +52,23 @@ __global__ void __launch_bounds__(64 * kTriLinesPerBlock) k_tridiag_x(
   const int L = (lane < P) ? min(M, n - s0) : 0;  // rows of this lane's segment
   const T* src = in + (size_t)line * n;
   // the segment's rows: a x_{r-1} + b x_r + c x_{r+1} = d (identity rows beyond L); the
-  // coefficients are formed in FP64 and rounded to T
+  // coefficients are formed in FP64 and rounded to T.  Every lane loads from an in-range
+  // row (rows past the line re-read its last one) and selects afterwards, so all the
+  // loads are in flight together instead of one branch and wait per row.
   T ra[M], rb[M], rc[M], rv[M];
 #pragma unroll
   for (int t = 0; t < M; ++t) {
-    const int r = s0 + t;
-    T a = 0, b = 1, c = 0, d = 0;
-    if (t < L) {
-      const double a64 = (r > 0) ? rdd[r] * rd[r] : 0.0;
-      const double c64 = (r + 1 < n) ? rdd[r + 1] * rd[r] : 0.0;
-      a = (T)a64;
-      c = (T)c64;
-      b = shift - (T)(a64 + c64);
-      d = src[r];
-      if (sing && r == 0) {
-        a = 0;
-        b = 1;
-        c = 0;
-        d = 0;
-      }
-    }
-    ra[t] = a;
-    rb[t] = b;
-    rc[t] = c;
-    rv[t] = d;
+    const int r = s0 + t, rr = min(r, n - 1);
+    const double rdr = rd[rr], rdd0 = rdd[rr], rdd1 = rdd[rr + 1];  // rdd has n + 1 entries
+    const T dr = src[rr];
+    const bool in = t < L;
+    const bool pin = sing && r == 0;
+    const double a64 = (in && r > 0) ? rdd0 * rdr : 0.0;
+    const double c64 = (in && r + 1 < n) ? rdd1 * rdr : 0.0;
+    ra[t] = pin ? T(0) : (T)a64;
+    rc[t] = pin ? T(0) : (T)c64;
+    rb[t] = (in && !pin) ? shift - (T)(a64 + c64) : T(1);
+    rv[t] = (in && !pin) ? dr : T(0);
   }
   // interior rows 0 .. q-1 in terms of the two segment ends z_{p-1} (previous lane's last
   // row) and z_p (own last row): x = Y - V z_{p-1} - W z_p
@@ -143,44 +136,40 @@ __global__ void __launch_bounds__(64 * kTriLinesPerBlock) k_tridiag_x(
     ga = -ce * Wn;
     dl = de - ae * Yl - ce * Yn;
   }
-  // cyclic reduction across the lanes (identity rows beyond P couple to nothing)
+  // cyclic reduction across the lanes (identity rows beyond P couple to nothing).  At step
+  // st a row couples to rows st below and above it; the lower coupling al is exactly zero
+  // on lanes below st and the upper one ga on lanes with no row st above (initially from
+  // the zero coefficients of the line's first and last rows, then because each update
+  // multiplies by them), so the products with the values a shuffle returns past the wave's
+  // ends vanish and the updates need no lane conditions.
   for (int st = 1; st < P; st <<= 1) {
     const T rbt = rcpx(bt);
-    T an = 0, gn = 0, bn = bt, dn = dl;
+    T an, gn, bn = bt, dn = dl;
     if constexpr (sizeof(T) == 8) {
       // each lane sends its row divided by its own diagonal: three values per direction
       // (12 LDS permutes per step instead of 16)
       const T as = al * rbt, gs = ga * rbt, ds = dl * rbt;
       const T am = __shfl_up(as, st), gm = __shfl_up(gs, st), dm = __shfl_up(ds, st);
       const T ap = __shfl_down(as, st), gp = __shfl_down(gs, st), dp = __shfl_down(ds, st);
-      if (lane >= st) {
-        an = -al * am;
-        bn -= al * gm;
-        dn -= al * dm;
-      }
-      if (lane + st < 64) {
-        gn = -ga * gp;
-        bn -= ga * ap;
-        dn -= ga * dp;
-      }
+      an = -al * am;
+      bn -= al * gm;
+      dn -= al * dm;
+      gn = -ga * gp;
+      bn -= ga * ap;
+      dn -= ga * dp;
     } else {
       // FP32: the neighbour's reciprocal travels separately, which keeps the mixed form's
       // solves as accurate as before the FP64 change (the sender-side products lost a factor
       // of about 1.5 in the first-pass divergence)
       const T am = __shfl_up(al, st), gm = __shfl_up(ga, st), dm = __shfl_up(dl, st), rm = __shfl_up(rbt, st);
       const T ap = __shfl_down(al, st), gp = __shfl_down(ga, st), dp = __shfl_down(dl, st), rp = __shfl_down(rbt, st);
-      if (lane >= st) {
-        const T k1 = al * rm;
-        an = -am * k1;
-        bn -= gm * k1;
-        dn -= dm * k1;
-      }
-      if (lane + st < 64) {
-        const T k2 = ga * rp;
-        gn = -gp * k2;
-        bn -= ap * k2;
-        dn -= dp * k2;
-      }
+      const T k1 = al * rm, k2 = ga * rp;
+      an = -am * k1;
+      bn -= gm * k1;
+      dn -= dm * k1;
+      gn = -gp * k2;
+      bn -= ap * k2;
+      dn -= dp * k2;
     }
     al = an;
     bt = bn;

@@ -127,7 +127,8 @@ __global__ void __launch_bounds__(kPlaneBlock) k_row_scan(const double* __restri
 // psi[k][0][i] = 0, psi[k][j + 1][i] = psi[k][j][i] - dy[j] w[k][j][i].
 // Block: 64 columns i x kColSeg segments of the j range (one wave per segment); each
 // wave sums its segment, the segment offsets go through LDS, then each wave writes its
-// running sums.  Loads are batched kColBatch at a time.
+// running sums.  Loads are batched kColBatch at a time, each from an in-range row (the
+// segment's last for the batch's surplus), so a batch's loads are in flight together.
 constexpr int kColSeg = 8, kColBatch = 8;
 
 __global__ void __launch_bounds__(64 * kColSeg) k_col_scan(const double* __restrict__ w,
@@ -144,7 +145,13 @@ __global__ void __launch_bounds__(64 * kColSeg) k_col_scan(const double* __restr
   for (int jb = j0; jb < j1; jb += kColBatch) {
     double x[kColBatch];
 #pragma unroll
-    for (int t = 0; t < kColBatch; ++t) x[t] = (col && jb + t < j1) ? dy[jb + t] * src[(size_t)(jb + t) * nx] : 0.0;
+    for (int t = 0; t < kColBatch; ++t) {
+      // in range, and masked by a product rather than a select (a select of a loaded value
+      // is turned back into a branch around the load): the batch's loads all go out
+      // before the sum waits
+      const int jr = min(jb + t, j1 - 1);
+      x[t] = dy[jr] * src[(size_t)jr * nx] * ((col && jb + t < j1) ? 1.0 : 0.0);
+    }
 #pragma unroll
     for (int t = 0; t < kColBatch; ++t) s += x[t];
   }
@@ -157,7 +164,10 @@ __global__ void __launch_bounds__(64 * kColSeg) k_col_scan(const double* __restr
   for (int jb = j0; jb < j1; jb += kColBatch) {
     double x[kColBatch];
 #pragma unroll
-    for (int t = 0; t < kColBatch; ++t) x[t] = (jb + t < j1) ? dy[jb + t] * src[(size_t)(jb + t) * nx] : 0.0;
+    for (int t = 0; t < kColBatch; ++t) {
+      const int jr = min(jb + t, j1 - 1);
+      x[t] = dy[jr] * src[(size_t)jr * nx] * ((jb + t < j1) ? 1.0 : 0.0);
+    }
 #pragma unroll
     for (int t = 0; t < kColBatch; ++t) {
       acc += x[t];

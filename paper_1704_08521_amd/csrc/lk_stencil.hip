@@ -428,8 +428,12 @@ __global__ void __launch_bounds__(kCorTX* kCorTY) k_correct(GridDev g, const dou
 }  // namespace
 
 // ==================================================================== launchers
-// Tile of the momentum stencil: TX x TY threads, kMomChunk planes per block.
-constexpr int kMomTX = 16, kMomTY = 8, kMomChunk = 24;
+// Tile of the momentum stencil: TX x TY threads; the nz + 1 planes are split into the
+// nearest whole number of kMomChunk-plane chunks, ceil((nz + 1) / that number) planes each
+// (the last takes the rest), one chunk per block.  Measured at
+// 200^3 (201 planes, same bits for every length): 12 planes 191-192 us, 14 196-198, 17
+// 193-195, 24 197-199, 29 197-198, 41 218; 8 and 10 (a last chunk of one plane) 197-201.
+constexpr int kMomTX = 16, kMomTY = 8, kMomChunk = 12;
 
 hipError_t launch_momentum(const GridDev& g, const double* a, const double* b, double* out, double rre, double s,
                            bool lid, double lid_u, double lid_v, hipStream_t st) {
@@ -437,14 +441,16 @@ hipError_t launch_momentum(const GridDev& g, const double* a, const double* b, d
   const VelLayout L = vel_layout(nx, ny, nz);
   if (8 * std::max(L.nu, std::max(L.nv, L.nw)) >= (size_t(1) << 31)) return hipErrorInvalidValue;
   const int nbx = (int)blocks_for(nx + 1, kMomTX), nby = (int)blocks_for(ny + 1, kMomTY);
-  const int nbz = (int)blocks_for(nz + 1, kMomChunk);
+  const int nch = std::max(1, (nz + 1 + kMomChunk / 2) / kMomChunk);
+  const int kchunk = (int)blocks_for(nz + 1, nch);
+  const int nbz = (int)blocks_for(nz + 1, kchunk);
   const dim3 grid(nbx * nby * nbz), block(kMomTX * kMomTY);
   if (lid)
     hipLaunchKernelGGL((k_momentum<true, kMomTX, kMomTY>), grid, block, 0, st, g, a, b, out, rre, s, lid_u, lid_v,
-                       kMomChunk, nbx, nby);
+                       kchunk, nbx, nby);
   else
     hipLaunchKernelGGL((k_momentum<false, kMomTX, kMomTY>), grid, block, 0, st, g, a, b, out, rre, s, 0.0, 0.0,
-                       kMomChunk, nbx, nby);
+                       kchunk, nbx, nby);
   return hipGetLastError();
 }
 
